@@ -1,0 +1,198 @@
+/*
+ * evp.h -- C-ABI of libevp.so: one time step of incompressible flow of an Oldroyd-B, FENE-P or
+ * Saramito elastoviscoplastic fluid on a uniform staggered grid, on one MI355X (gfx950).
+ *
+ * The method is the single-phase Eulerian part of Izbassarov et al., "Computational modeling of
+ * multiphase viscoelastic and elastoviscoplastic flows":
+ *   - unknowns u, p and the conformation tensor B of Sec. 2, Eqs. (mainNS) and (SRM2);
+ *   - the closures F, a and the B <-> tau relation of Table 1;
+ *   - the staggered grid and differences of Sec. 3 (velocities on faces; p and B at centres;
+ *     second-order central differences; fifth-order WENO for u.grad(B), Sec. 3.1);
+ *   - the Adams-Bashforth step and Chorin projection of Sec. 3.2.2, Eqs. (ab2tau), (ab2), (rt),
+ *     (ru), (var poisson), (projection), with constant rho, g = 0 and f a body force; the pressure
+ *     equation is solved with FFTs in periodic directions and a tridiagonal solve across walls.
+ *
+ * Conventions shared by every call
+ *   - Status: 0 (EVP_OK) or a negative EVP_ERR_* code.  No call throws, aborts or prints;
+ *     evp_last_error() returns a thread-local text describing the last failure.
+ *   - Memory: the caller owns all device memory (the workspace and every I/O buffer); the library
+ *     never allocates or frees device memory.  It owns only the opaque host-side evp_grid.
+ *   - Streams: every call enqueues work on the HIP stream given at creation (or by
+ *     evp_set_stream) and returns without waiting, except evp_health and evp_profile_read,
+ *     which wait for the stream.  The caller synchronises before reading output buffers.
+ *   - I/O arrays are device pointers to dense FP64 arrays [nz][ny][nx] (x fastest) in every
+ *     precision mode.  u[k][j][i] is the x-velocity on the +x face of cell (i,j,k) (x = (i+1)dx,
+ *     y = y0 + (j+1/2)dy, z = (k+1/2)dz); v and w sit on the +y and +z faces likewise; p and the
+ *     six planes of B (order xx, xy, xz, yy, yz, zz) sit at cell centres.  With walls, y0 =
+ *     -ly/2, the bottom wall face is implicit and v[k][ny-1][i] is the top wall face (always 0);
+ *     periodic y has y0 = 0.
+ */
+#ifndef EVP_H
+#define EVP_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define EVP_OK             0
+#define EVP_ERR_ARG       -1   /* bad size, spacing, parameter, pointer or flag */
+#define EVP_ERR_WORKSPACE -2   /* workspace too small or not 256-byte aligned */
+#define EVP_ERR_STATE     -3   /* step/project/read before set_rheology or write_fields */
+#define EVP_ERR_SHAPE     -4   /* grids of one batch differ in shape, precision or stream */
+#define EVP_ERR_HIP       -5   /* a HIP runtime call or kernel launch failed */
+
+/* boundary condition in y */
+#define EVP_PERIODIC 0         /* periodic in x, y, z */
+#define EVP_WALLS    1         /* periodic in x, z; no-slip walls at y = -ly/2 and y = +ly/2 */
+
+/* precision of the stress transport and momentum stencils (the projection is always FP64) */
+#define EVP_FP64  0
+#define EVP_MIXED 1            /* B - I, RT, RU stored and computed in FP32; u, u*, p in FP64 */
+
+/* constitutive models, Table 1 */
+#define EVP_OLDROYD_B 0
+#define EVP_FENE_P    1
+#define EVP_SARAMITO  2
+
+/* body force f of Eq. (NS) */
+#define EVP_FORCE_NONE       0
+#define EVP_FORCE_CONST_X    1 /* f_x = amp */
+#define EVP_FORCE_SIN_X_OF_Y 2 /* f_x = amp * sin(ky * y), sampled at the u-face y */
+
+/* evp_step flags */
+#define EVP_FREEZE_VELOCITY      1u  /* advance B only, u unchanged: the "uncoupled" shear test
+                                        of Sec. 4.1.3 */
+#define EVP_STOP_AFTER_PREDICTOR 2u  /* skip the projection: u <- u* (stage check) */
+
+/* evp_read_fields mask bits */
+#define EVP_READ_U    1u
+#define EVP_READ_V    2u
+#define EVP_READ_W    4u
+#define EVP_READ_P    8u
+#define EVP_READ_B   16u
+#define EVP_READ_HIST 32u
+
+/* largest batch of evp_step_batch */
+#define EVP_MAX_BATCH 32
+
+/* kernel classes reported by evp_profile_read */
+#define EVP_K_PREDICTOR 0      /* fused stress + momentum stencil */
+#define EVP_K_DIV_FFTX  1      /* Poisson right-hand side + forward x transform */
+#define EVP_K_FFT_FWD   2      /* forward transform along y (periodic) or z (walls) */
+#define EVP_K_SOLVE     3      /* z transform + spectral division (periodic) / Thomas (walls) */
+#define EVP_K_FFT_INV   4      /* inverse transform along y (periodic) or z (walls) */
+#define EVP_K_IFFTX     5      /* inverse x transform -> p */
+#define EVP_K_CORRECT   6      /* u = u* - (dt/rho) grad p */
+#define EVP_K_COUNT     7
+
+typedef struct evp_grid evp_grid;
+
+typedef struct {
+    long long nonfinite;   /* cells where B or a velocity component is not finite */
+    long long det_le0;     /* cells with det(B) <= 0 (loss of positive definiteness, Sec. 3.1) */
+    long long trace_ge95;  /* FENE-P cells with tr(B) >= 0.95 L^2 (Sec. 3.1); 0 for other models */
+    double max_div;        /* max |D_h u| over cells */
+    double energy;         /* 1/2 sum(u^2 + v^2 + w^2) dx dy dz over faces */
+} evp_health_t;
+
+typedef struct {
+    long long launches[EVP_K_COUNT];  /* launches timed since evp_profile(g, 1) */
+    double ms[EVP_K_COUNT];           /* summed HIP-event time per kernel class, milliseconds */
+} evp_profile_t;
+
+/* Text for a status code (static storage). */
+const char* evp_error_string(int status);
+
+/* Thread-local description of the most recent failure on this thread ("" if none). */
+const char* evp_last_error(void);
+
+/* Bytes of device workspace a grid of this shape needs (0 if the arguments are invalid).
+ * nx, nz: even, 8..512 and of the form 2^a 3^b (FFT directions); ny: 8..512 of the same form
+ * when bc_y is EVP_PERIODIC, 4..1024 (any) with EVP_WALLS. */
+size_t evp_workspace_bytes(int nx, int ny, int nz, int bc_y, int precision);
+
+/* Create a grid of nx x ny x nz cells in a box lx x ly x lz.  dev_workspace: device memory of at
+ * least evp_workspace_bytes() bytes, 256-byte aligned, owned by the caller and kept alive until
+ * evp_destroy_grid.  hip_stream: a hipStream_t (NULL = the null stream).  On success *out holds a
+ * new grid with u = 0, B = I, p = 0, no rheology set.  Enqueues table uploads on the stream. */
+int evp_create_grid(int nx, int ny, int nz, double lx, double ly, double lz, int bc_y,
+                    int precision, void* dev_workspace, size_t workspace_bytes, void* hip_stream,
+                    evp_grid** out);
+
+/* Change the stream later calls enqueue on (the caller orders it after earlier work). */
+int evp_set_stream(evp_grid* g, void* hip_stream);
+
+/* Material of Eq. (NS) and Table 1: density rho > 0, solvent viscosity mu_s >= 0, polymer
+ * viscosity mu_p >= 0, relaxation time lambda > 0, yield stress tau_y >= 0 (Saramito only),
+ * extensibility L2 > 3 (FENE-P only). */
+int evp_set_rheology(evp_grid* g, int model, double rho, double mu_s, double mu_p, double lambda,
+                     double tau_y, double L2);
+
+/* Body force f of Eq. (NS), one of EVP_FORCE_*. */
+int evp_set_forcing(evp_grid* g, int kind, double amp, double ky);
+
+/* Wall velocities (EVP_WALLS only): x- and z-velocity of the bottom (y = -ly/2) and top walls. */
+int evp_set_walls(evp_grid* g, double u_bot, double u_top, double w_bot, double w_top);
+
+/* Load the state: u, v, w (FP64 device arrays, layout above), B6 (six FP64 planes).  hist, if not
+ * NULL, holds the nine planes RT_xx..RT_zz, RU_x, RU_y, RU_z of the previous step (Eqs. rt, ru) so
+ * that the next step is a full AB2 step; with NULL the history is cleared and the next step is a
+ * forward-Euler start.  With walls v on the top wall face is forced to 0.  Pointers are read on
+ * the stream; they must stay valid until it reaches this point. */
+int evp_write_fields(evp_grid* g, const double* u, const double* v, const double* w,
+                     const double* B6, const double* hist);
+
+/* Project the current velocity onto discretely divergence-free fields (Eqs. var poisson and
+ * projection with u* = u and dt = 1); p is set to the potential removed. */
+int evp_project(evp_grid* g);
+
+/* Advance nsteps steps of size dt > 0 (Sec. 3.2.2): predictor (stress transport, Eq. ab2tau;
+ * momentum, Eq. ab2), then the Poisson solve and the velocity correction.  flags: EVP_FREEZE_*,
+ * EVP_STOP_AFTER_PREDICTOR. */
+int evp_step(evp_grid* g, double dt, int nsteps, unsigned flags);
+
+/* The same for count <= EVP_MAX_BATCH grids of identical shape, boundary type, precision and
+ * stream, each with its own rheology, forcing, walls and state: every kernel is launched once for
+ * the whole batch.  Results are identical to count separate evp_step calls. */
+int evp_step_batch(evp_grid* const* grids, int count, double dt, int nsteps, unsigned flags);
+
+/* Copy the selected fields (mask of EVP_READ_*) into FP64 device arrays (NULL for unselected):
+ * u, v, w, p: one plane each; B6: six planes; hist: nine planes as in evp_write_fields. */
+int evp_read_fields(evp_grid* g, unsigned mask, double* u, double* v, double* w, double* p,
+                    double* B6, double* hist);
+
+/* Bytes of an opaque checkpoint of this grid's state (u, v, w, p, B, AB2 history, step count). */
+size_t evp_state_bytes(const evp_grid* g);
+
+/* Copy the state, bit for bit, into dst (device memory of evp_state_bytes() bytes, 256-byte
+ * aligned, owned by the caller).  Waits for the stream before returning. */
+int evp_save_state(evp_grid* g, void* dst, size_t bytes);
+
+/* Restore a state saved from a grid of the same shape, boundary type and precision; the next
+ * step continues exactly as the saved grid would have.  Waits for the stream. */
+int evp_load_state(evp_grid* g, const void* src, size_t bytes);
+
+/* Diagnostics of the current state; waits for the stream, *out is host memory. */
+int evp_health(evp_grid* g, evp_health_t* out);
+
+/* Steps taken since the last evp_write_fields (AB2 bookkeeping). */
+int evp_step_count(evp_grid* g, long long* out);
+
+/* Turn per-kernel HIP-event timing on (1, counters reset) or off (0).  While on, every kernel
+ * launch of evp_step/evp_step_batch is bracketed by events on the grid's stream. */
+int evp_profile(evp_grid* g, int enable);
+
+/* Sum the recorded kernel times (waits for the stream). */
+int evp_profile_read(evp_grid* g, evp_profile_t* out);
+
+/* Release the host-side grid (the workspace stays the caller's).  NULL is accepted. */
+int evp_destroy_grid(evp_grid* g);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EVP_H */

@@ -1,0 +1,653 @@
+// Host side of libevp.so: argument checks, workspace carving, FP64 tables (twiddles, Laplacian
+// eigenvalues, Thomas pivots), the step schedule of Sec. 3.2.2 and per-kernel event timing.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "evp_internal.h"
+
+using evp::Batch;
+using evp::Desc;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg)
+{
+    g_last_error = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what)
+{
+    return fail(EVP_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+constexpr size_t kAlign = 256;
+constexpr int kRedDoubles = 1024 * 5 + 8;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+bool is_23_smooth(int n)
+{
+    if (n < 1) return false;
+    while (n % 2 == 0) n /= 2;
+    while (n % 3 == 0) n /= 3;
+    return n == 1;
+}
+
+struct Layout {
+    size_t desc, u, v, w, us, vs, ws, p, B0, B1, RT, RU, spec, twx, twy, twz, eigx, eigy, eigz,
+        piv, red, total;
+    long long ps;
+};
+
+bool shape_ok(int nx, int ny, int nz, int bc_y, int precision, std::string* why)
+{
+    char buf[256];
+    if (bc_y != EVP_PERIODIC && bc_y != EVP_WALLS) { *why = "bc_y must be EVP_PERIODIC or EVP_WALLS"; return false; }
+    if (precision != EVP_FP64 && precision != EVP_MIXED) { *why = "precision must be EVP_FP64 or EVP_MIXED"; return false; }
+    if (nx % 2 != 0 || !evp::fft_size_supported(nx)) {
+        snprintf(buf, sizeof buf, "nx=%d: must be an even FFT size of the form 2^a 3^b in [8, 512]", nx);
+        *why = buf; return false;
+    }
+    if (!evp::fft_size_supported(nz)) {
+        snprintf(buf, sizeof buf, "nz=%d: must be an FFT size of the form 2^a 3^b in [8, 512]", nz);
+        *why = buf; return false;
+    }
+    if (bc_y == EVP_PERIODIC && !evp::fft_size_supported(ny)) {
+        snprintf(buf, sizeof buf, "ny=%d: periodic y needs an FFT size of the form 2^a 3^b in [8, 512]", ny);
+        *why = buf; return false;
+    }
+    if (bc_y == EVP_WALLS && (ny < 4 || ny > 1024)) {
+        snprintf(buf, sizeof buf, "ny=%d: walls need 4 <= ny <= 1024", ny);
+        *why = buf; return false;
+    }
+    return true;
+}
+
+Layout make_layout(int nx, int ny, int nz, int bc_y, int precision)
+{
+    Layout L{};
+    const size_t n = (size_t)nx * ny * nz;
+    const size_t nh = (size_t)nx / 2 + 1;
+    const size_t tsz = precision == EVP_MIXED ? 4 : 8;
+    L.ps = (long long)((n + 63) / 64 * 64);
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off += align_up(bytes); return o; };
+    L.desc = take(4096);
+    L.u = take(n * 8); L.v = take(n * 8); L.w = take(n * 8);
+    L.us = take(n * 8); L.vs = take(n * 8); L.ws = take(n * 8);
+    L.p = take(n * 8);
+    L.B0 = take(6 * (size_t)L.ps * tsz);
+    L.B1 = take(6 * (size_t)L.ps * tsz);
+    L.RT = take(6 * (size_t)L.ps * tsz);
+    L.RU = take(3 * (size_t)L.ps * tsz);
+    L.spec = take(nh * ny * nz * 16);
+    L.twx = take((size_t)nx * 16); L.twy = take((size_t)ny * 16); L.twz = take((size_t)nz * 16);
+    L.eigx = take(nh * 8); L.eigy = take((size_t)ny * 8); L.eigz = take((size_t)nz * 8);
+    L.piv = take(bc_y == EVP_WALLS ? ((size_t)nz / 2 + 1) * ny * nh * 8 : 8);
+    L.red = take(kRedDoubles * 8);
+    L.total = off;
+    return L;
+}
+
+struct PendingEvent {
+    int cls;
+    hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct evp_grid {
+    int nx, ny, nz, bc, precision;
+    double lx, ly, lz;
+    hipStream_t stream;
+    char* ws;
+    size_t ws_bytes;
+    Layout L;
+    Desc h;            // host mirror of the device descriptor
+    Desc* d;           // device descriptor
+    int parity;
+    bool have_hist, have_rheo, have_fields;
+    long long nstep;
+    bool prof;
+    std::vector<PendingEvent> pending;
+    std::vector<hipEvent_t> free_events;
+    long long prof_launches[EVP_K_COUNT];
+    double prof_ms[EVP_K_COUNT];
+};
+
+namespace {
+
+int upload_desc(evp_grid* g)
+{
+    hipError_t e = hipMemcpyAsync(g->d, &g->h, sizeof(Desc), hipMemcpyHostToDevice, g->stream);
+    if (e != hipSuccess) return hip_fail(e, "descriptor upload");
+    e = hipStreamSynchronize(g->stream);
+    if (e != hipSuccess) return hip_fail(e, "descriptor upload (sync)");
+    return EVP_OK;
+}
+
+hipEvent_t get_event(evp_grid* g)
+{
+    if (!g->free_events.empty()) {
+        hipEvent_t e = g->free_events.back();
+        g->free_events.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+void fold_events(evp_grid* g)
+{
+    for (auto& pe : g->pending) {
+        float ms = 0.0f;
+        if (hipEventSynchronize(pe.b) == hipSuccess && hipEventElapsedTime(&ms, pe.a, pe.b) == hipSuccess) {
+            g->prof_ms[pe.cls] += ms;
+            g->prof_launches[pe.cls] += 1;
+        }
+        g->free_events.push_back(pe.a);
+        g->free_events.push_back(pe.b);
+    }
+    g->pending.clear();
+}
+
+// Launch one kernel class, bracketed by events when profiling.
+template <typename F>
+int timed(evp_grid* g, int cls, F&& launch)
+{
+    hipEvent_t a = nullptr, b = nullptr;
+    if (g->prof) {
+        if (g->pending.size() >= 2048) fold_events(g);
+        a = get_event(g);
+        b = get_event(g);
+        if (a && b) (void)hipEventRecord(a, g->stream);
+    }
+    hipError_t e = launch();
+    if (g->prof && a && b) {
+        (void)hipEventRecord(b, g->stream);
+        g->pending.push_back({cls, a, b});
+    }
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return EVP_OK;
+}
+
+int projection(evp_grid* g0, const Batch& b)
+{
+    const int nx = g0->nx, ny = g0->ny, nz = g0->nz;
+    hipStream_t s = g0->stream;
+    int r;
+    if ((r = timed(g0, EVP_K_DIV_FFTX, [&] { return evp::launch_div_fftx(b, nx, ny, nz, s); }))) return r;
+    if (g0->bc == EVP_PERIODIC) {
+        if ((r = timed(g0, EVP_K_FFT_FWD, [&] { return evp::launch_fft_strided(b, nx, ny, nz, 1, false, s); }))) return r;
+        if ((r = timed(g0, EVP_K_SOLVE, [&] { return evp::launch_solve_periodic(b, nx, ny, nz, s); }))) return r;
+        if ((r = timed(g0, EVP_K_FFT_INV, [&] { return evp::launch_fft_strided(b, nx, ny, nz, 1, true, s); }))) return r;
+    } else {
+        if ((r = timed(g0, EVP_K_FFT_FWD, [&] { return evp::launch_fft_strided(b, nx, ny, nz, 2, false, s); }))) return r;
+        if ((r = timed(g0, EVP_K_SOLVE, [&] { return evp::launch_thomas(b, nx, ny, nz, s); }))) return r;
+        if ((r = timed(g0, EVP_K_FFT_INV, [&] { return evp::launch_fft_strided(b, nx, ny, nz, 2, true, s); }))) return r;
+    }
+    if ((r = timed(g0, EVP_K_IFFTX, [&] { return evp::launch_ifftx(b, nx, ny, nz, s); }))) return r;
+    if ((r = timed(g0, EVP_K_CORRECT, [&] { return evp::launch_correct(b, nx, ny, nz, s); }))) return r;
+    return EVP_OK;
+}
+
+void build_tables(const evp_grid* g, std::vector<char>& host, size_t base)
+{
+    // host image of the table region [twx, red) of the workspace
+    const Layout& L = g->L;
+    host.assign(L.red - base, 0);
+    auto tw = [&](size_t off, int n) {
+        double* t = reinterpret_cast<double*>(host.data() + (off - base));
+        for (int k = 0; k < n; ++k) {
+            const double ang = -2.0 * M_PI * (double)k / (double)n;
+            t[2 * k] = std::cos(ang);
+            t[2 * k + 1] = std::sin(ang);
+        }
+    };
+    tw(L.twx, g->nx); tw(L.twy, g->ny); tw(L.twz, g->nz);
+    auto eig = [&](size_t off, int count, int n, double h) {
+        double* t = reinterpret_cast<double*>(host.data() + (off - base));
+        for (int k = 0; k < count; ++k) {
+            const double s = std::sin(M_PI * (double)k / (double)n);
+            t[k] = -(4.0 / (h * h)) * s * s;
+        }
+    };
+    const int nh = g->nx / 2 + 1;
+    eig(L.eigx, nh, g->nx, g->h.dx);
+    eig(L.eigy, g->ny, g->ny, g->h.dy);
+    eig(L.eigz, g->nz, g->nz, g->h.dz);
+    if (g->bc == EVP_WALLS) {
+        // LU pivots of the Neumann tridiagonal system of every (kx, |kz|) mode:
+        // a = c = 1/dy^2, b_j = -2/dy^2 + mu (first and last row -1/dy^2 + mu), mu = lx + lz
+        const double* ex = reinterpret_cast<const double*>(host.data() + (L.eigx - base));
+        const double* ez = reinterpret_cast<const double*>(host.data() + (L.eigz - base));
+        double* piv = reinterpret_cast<double*>(host.data() + (L.piv - base));
+        const int ny = g->ny;
+        const double a = 1.0 / (g->h.dy * g->h.dy);
+        for (int kzs = 0; kzs <= g->nz / 2; ++kzs) {
+            for (int kx = 0; kx < nh; ++kx) {
+                const double mu = ex[kx] + ez[kzs];
+                double cprev = 0.0;
+                for (int j = 0; j < ny; ++j) {
+                    double bj = -2.0 * a + mu;
+                    if (j == 0 || j == ny - 1) bj += a;
+                    const double inv = 1.0 / (bj - a * cprev);
+                    piv[((size_t)kzs * ny + j) * nh + kx] = inv;
+                    cprev = a * inv;
+                }
+                if (kx == 0 && kzs == 0) piv[(size_t)(ny - 1) * nh] = 0.0;   // singular mode: p_{ny-1} = 0
+            }
+        }
+    }
+}
+
+int check_grid(evp_grid* g)
+{
+    if (!g) return fail(EVP_ERR_ARG, "null grid");
+    return EVP_OK;
+}
+
+int enqueue_steps(evp_grid* const* gs, int count, double dt, int nsteps, unsigned flags)
+{
+    evp_grid* g0 = gs[0];
+    const bool freeze = (flags & EVP_FREEZE_VELOCITY) != 0;
+    const bool stop = (flags & EVP_STOP_AFTER_PREDICTOR) != 0;
+    for (int s = 0; s < nsteps; ++s) {
+        Batch b{};
+        b.count = count;
+        for (int i = 0; i < count; ++i) {
+            b.d[i] = gs[i]->d;
+            b.dt[i] = dt;
+            b.state[i] = gs[i]->parity | (gs[i]->have_hist ? 0 : evp::ST_EULER);
+        }
+        int r = timed(g0, EVP_K_PREDICTOR, [&] {
+            return evp::launch_predictor(b, g0->precision, g0->nx, g0->ny, g0->nz, freeze, g0->stream);
+        });
+        if (r) return r;
+        if (stop && !freeze) {
+            hipError_t e = evp::launch_copy_ustar(b, g0->nx, g0->ny, g0->nz, true, g0->stream);
+            if (e != hipSuccess) return hip_fail(e, "copy u*");
+        } else if (!freeze) {
+            if ((r = projection(g0, b))) return r;
+        }
+        for (int i = 0; i < count; ++i) {
+            gs[i]->parity ^= 1;
+            gs[i]->have_hist = true;
+            gs[i]->nstep += 1;
+        }
+    }
+    return EVP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* evp_error_string(int status)
+{
+    switch (status) {
+    case EVP_OK: return "ok";
+    case EVP_ERR_ARG: return "invalid argument";
+    case EVP_ERR_WORKSPACE: return "workspace too small or misaligned";
+    case EVP_ERR_STATE: return "grid not ready (set_rheology / write_fields missing)";
+    case EVP_ERR_SHAPE: return "batch grids differ in shape, precision or stream";
+    case EVP_ERR_HIP: return "HIP runtime error";
+    default: return "unknown status";
+    }
+}
+
+const char* evp_last_error(void) { return g_last_error.c_str(); }
+
+size_t evp_workspace_bytes(int nx, int ny, int nz, int bc_y, int precision)
+{
+    std::string why;
+    if (!shape_ok(nx, ny, nz, bc_y, precision, &why)) return 0;
+    return make_layout(nx, ny, nz, bc_y, precision).total;
+}
+
+int evp_create_grid(int nx, int ny, int nz, double lx, double ly, double lz, int bc_y,
+                    int precision, void* dev_workspace, size_t workspace_bytes, void* hip_stream,
+                    evp_grid** out)
+{
+    g_last_error.clear();
+    if (!out) return fail(EVP_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    std::string why;
+    if (!shape_ok(nx, ny, nz, bc_y, precision, &why)) return fail(EVP_ERR_ARG, why);
+    if (!(lx > 0) || !(ly > 0) || !(lz > 0) || !std::isfinite(lx) || !std::isfinite(ly) || !std::isfinite(lz))
+        return fail(EVP_ERR_ARG, "box lengths must be finite and positive");
+    Layout L = make_layout(nx, ny, nz, bc_y, precision);
+    if (!dev_workspace) return fail(EVP_ERR_WORKSPACE, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(dev_workspace) % kAlign != 0)
+        return fail(EVP_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    if (workspace_bytes < L.total) {
+        char buf[160];
+        snprintf(buf, sizeof buf, "workspace has %zu bytes, needs %zu", workspace_bytes, L.total);
+        return fail(EVP_ERR_WORKSPACE, buf);
+    }
+    evp_grid* g = new (std::nothrow) evp_grid();
+    if (!g) return fail(EVP_ERR_ARG, "host allocation failed");
+    g->nx = nx; g->ny = ny; g->nz = nz; g->bc = bc_y; g->precision = precision;
+    g->lx = lx; g->ly = ly; g->lz = lz;
+    g->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    g->ws = reinterpret_cast<char*>(dev_workspace);
+    g->ws_bytes = workspace_bytes;
+    g->L = L;
+    Desc& h = g->h;
+    std::memset(&h, 0, sizeof h);
+    h.nx = nx; h.ny = ny; h.nz = nz; h.nh = nx / 2 + 1;
+    h.walls = bc_y == EVP_WALLS;
+    h.precision = precision;
+    h.model = EVP_OLDROYD_B;
+    h.force_kind = EVP_FORCE_NONE;
+    h.ncell = (long long)nx * ny * nz;
+    h.ps = L.ps;
+    h.dx = lx / nx; h.dy = ly / ny; h.dz = lz / nz;
+    h.idx = 1.0 / h.dx; h.idy = 1.0 / h.dy; h.idz = 1.0 / h.dz;
+    h.y0 = bc_y == EVP_WALLS ? -0.5 * ly : 0.0;
+    h.rho = 1.0; h.inv_rho = 1.0; h.lam = 1.0; h.inv_lam = 1.0; h.L2 = 1e4;
+    h.a_fene = h.L2 / (h.L2 - 3.0);
+    char* w = g->ws;
+    h.u = (double*)(w + L.u); h.v = (double*)(w + L.v); h.w = (double*)(w + L.w);
+    h.us = (double*)(w + L.us); h.vs = (double*)(w + L.vs); h.ws = (double*)(w + L.ws);
+    h.p = (double*)(w + L.p);
+    h.Bt[0] = w + L.B0; h.Bt[1] = w + L.B1;
+    h.RT = w + L.RT; h.RU = w + L.RU;
+    h.spec = (double2*)(w + L.spec);
+    h.twx = (const double2*)(w + L.twx); h.twy = (const double2*)(w + L.twy); h.twz = (const double2*)(w + L.twz);
+    h.eigx = (const double*)(w + L.eigx); h.eigy = (const double*)(w + L.eigy); h.eigz = (const double*)(w + L.eigz);
+    h.piv = (const double*)(w + L.piv);
+    h.red = (double*)(w + L.red);
+    g->d = (Desc*)(w + L.desc);
+    g->parity = 0;
+
+    // zero state (u = 0, B - I = 0, histories 0, p = 0) and upload tables
+    hipError_t e = hipMemsetAsync(w + L.u, 0, L.spec - L.u, g->stream);
+    if (e != hipSuccess) { delete g; return hip_fail(e, "workspace clear"); }
+    std::vector<char> tables;
+    build_tables(g, tables, L.twx);
+    e = hipMemcpyAsync(w + L.twx, tables.data(), tables.size(), hipMemcpyHostToDevice, g->stream);
+    if (e != hipSuccess) { delete g; return hip_fail(e, "table upload"); }
+    int r = upload_desc(g);   // synchronises the stream (tables host buffer is released after)
+    if (r) { delete g; return r; }
+    *out = g;
+    return EVP_OK;
+}
+
+int evp_set_stream(evp_grid* g, void* hip_stream)
+{
+    if (int r = check_grid(g)) return r;
+    g->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    return EVP_OK;
+}
+
+int evp_set_rheology(evp_grid* g, int model, double rho, double mu_s, double mu_p, double lambda,
+                     double tau_y, double L2)
+{
+    if (int r = check_grid(g)) return r;
+    if (model != EVP_OLDROYD_B && model != EVP_FENE_P && model != EVP_SARAMITO)
+        return fail(EVP_ERR_ARG, "unknown model");
+    if (!(rho > 0) || !(mu_s >= 0) || !(mu_p >= 0) || !(lambda > 0) || !(tau_y >= 0) ||
+        !std::isfinite(rho) || !std::isfinite(mu_s) || !std::isfinite(mu_p) || !std::isfinite(lambda) ||
+        !std::isfinite(tau_y))
+        return fail(EVP_ERR_ARG, "need rho > 0, mu_s >= 0, mu_p >= 0, lambda > 0, tau_y >= 0 (finite)");
+    if (model == EVP_FENE_P && !(L2 > 3.0 && std::isfinite(L2)))
+        return fail(EVP_ERR_ARG, "FENE-P needs a finite L2 > 3");
+    Desc& h = g->h;
+    h.model = model;
+    h.rho = rho; h.inv_rho = 1.0 / rho;
+    h.mu_s = mu_s; h.mu_p = mu_p;
+    h.lam = lambda; h.inv_lam = 1.0 / lambda;
+    h.G = mu_p / lambda;
+    h.tau_y = model == EVP_SARAMITO ? tau_y : 0.0;
+    h.L2 = model == EVP_FENE_P ? L2 : 1e4;
+    h.a_fene = h.L2 / (h.L2 - 3.0);
+    int r = upload_desc(g);
+    if (r) return r;
+    g->have_rheo = true;
+    return EVP_OK;
+}
+
+int evp_set_forcing(evp_grid* g, int kind, double amp, double ky)
+{
+    if (int r = check_grid(g)) return r;
+    if (kind != EVP_FORCE_NONE && kind != EVP_FORCE_CONST_X && kind != EVP_FORCE_SIN_X_OF_Y)
+        return fail(EVP_ERR_ARG, "unknown forcing kind");
+    if (!std::isfinite(amp) || !std::isfinite(ky)) return fail(EVP_ERR_ARG, "forcing must be finite");
+    g->h.force_kind = kind;
+    g->h.force_amp = amp;
+    g->h.force_ky = ky;
+    return upload_desc(g);
+}
+
+int evp_set_walls(evp_grid* g, double u_bot, double u_top, double w_bot, double w_top)
+{
+    if (int r = check_grid(g)) return r;
+    if (g->bc != EVP_WALLS) return fail(EVP_ERR_ARG, "evp_set_walls needs EVP_WALLS");
+    if (!std::isfinite(u_bot) || !std::isfinite(u_top) || !std::isfinite(w_bot) || !std::isfinite(w_top))
+        return fail(EVP_ERR_ARG, "wall velocities must be finite");
+    g->h.u_bot = u_bot; g->h.u_top = u_top; g->h.w_bot = w_bot; g->h.w_top = w_top;
+    return upload_desc(g);
+}
+
+int evp_write_fields(evp_grid* g, const double* u, const double* v, const double* w,
+                     const double* B6, const double* hist)
+{
+    if (int r = check_grid(g)) return r;
+    if (!u || !v || !w || !B6) return fail(EVP_ERR_ARG, "u, v, w and B6 must be non-NULL");
+    hipError_t e = evp::launch_write_fields(g->d, g->precision, g->h.ncell, g->ny, g->nx,
+                                            g->h.walls, g->parity, u, v, w, B6, hist, g->stream);
+    if (e != hipSuccess) return hip_fail(e, "write_fields");
+    g->have_hist = hist != nullptr;
+    g->have_fields = true;
+    g->nstep = 0;
+    return EVP_OK;
+}
+
+int evp_project(evp_grid* g)
+{
+    if (int r = check_grid(g)) return r;
+    if (!g->have_fields) return fail(EVP_ERR_STATE, "project before write_fields");
+    Batch b{};
+    b.count = 1;
+    b.d[0] = g->d;
+    b.dt[0] = 1.0;
+    b.state[0] = g->parity;
+    hipError_t e = evp::launch_copy_ustar(b, g->nx, g->ny, g->nz, false, g->stream);
+    if (e != hipSuccess) return hip_fail(e, "copy u -> u*");
+    const bool prof = g->prof;
+    g->prof = false;
+    int r = projection(g, b);
+    g->prof = prof;
+    return r;
+}
+
+int evp_step(evp_grid* g, double dt, int nsteps, unsigned flags)
+{
+    if (int r = check_grid(g)) return r;
+    evp_grid* gs[1] = {g};
+    return evp_step_batch(gs, 1, dt, nsteps, flags);
+}
+
+int evp_step_batch(evp_grid* const* grids, int count, double dt, int nsteps, unsigned flags)
+{
+    g_last_error.clear();
+    if (!grids || count < 1 || count > EVP_MAX_BATCH)
+        return fail(EVP_ERR_ARG, "need 1 <= count <= EVP_MAX_BATCH grids");
+    if (!(dt > 0) || !std::isfinite(dt)) return fail(EVP_ERR_ARG, "dt must be finite and > 0");
+    if (nsteps < 0) return fail(EVP_ERR_ARG, "nsteps must be >= 0");
+    if (flags & ~(EVP_FREEZE_VELOCITY | EVP_STOP_AFTER_PREDICTOR)) return fail(EVP_ERR_ARG, "unknown flag");
+    const evp_grid* g0 = grids[0];
+    if (!g0) return fail(EVP_ERR_ARG, "null grid in batch");
+    for (int i = 0; i < count; ++i) {
+        const evp_grid* g = grids[i];
+        if (!g) return fail(EVP_ERR_ARG, "null grid in batch");
+        for (int k = 0; k < i; ++k)
+            if (grids[k] == g) return fail(EVP_ERR_ARG, "a grid appears twice in the batch");
+        if (g->nx != g0->nx || g->ny != g0->ny || g->nz != g0->nz || g->bc != g0->bc ||
+            g->precision != g0->precision || g->stream != g0->stream)
+            return fail(EVP_ERR_SHAPE, "batch grids must share shape, boundary type, precision and stream");
+        if (!g->have_rheo) return fail(EVP_ERR_STATE, "step before set_rheology");
+        if (!g->have_fields) return fail(EVP_ERR_STATE, "step before write_fields");
+    }
+    return enqueue_steps(const_cast<evp_grid* const*>(grids), count, dt, nsteps, flags);
+}
+
+int evp_read_fields(evp_grid* g, unsigned mask, double* u, double* v, double* w, double* p,
+                    double* B6, double* hist)
+{
+    if (int r = check_grid(g)) return r;
+    if (mask & ~63u) return fail(EVP_ERR_ARG, "unknown mask bit");
+    if (((mask & EVP_READ_U) && !u) || ((mask & EVP_READ_V) && !v) || ((mask & EVP_READ_W) && !w) ||
+        ((mask & EVP_READ_P) && !p) || ((mask & EVP_READ_B) && !B6) || ((mask & EVP_READ_HIST) && !hist))
+        return fail(EVP_ERR_ARG, "a selected output pointer is NULL");
+    if (mask == 0) return EVP_OK;
+    hipError_t e = evp::launch_read_fields(g->d, g->precision, g->h.ncell, g->parity, mask, u, v,
+                                           w, p, B6, hist, g->stream);
+    if (e != hipSuccess) return hip_fail(e, "read_fields");
+    return EVP_OK;
+}
+
+int evp_health(evp_grid* g, evp_health_t* out)
+{
+    if (int r = check_grid(g)) return r;
+    if (!out) return fail(EVP_ERR_ARG, "out is NULL");
+    hipError_t e = evp::launch_health(g->d, g->precision, g->nx, g->ny, g->nz, g->parity, nullptr, g->stream);
+    if (e != hipSuccess) return hip_fail(e, "health");
+    double res[5];
+    e = hipMemcpyAsync(res, g->h.red + 1024 * 5, sizeof res, hipMemcpyDeviceToHost, g->stream);
+    if (e != hipSuccess) return hip_fail(e, "health copy");
+    e = hipStreamSynchronize(g->stream);
+    if (e != hipSuccess) return hip_fail(e, "health sync");
+    out->nonfinite = (long long)res[0];
+    out->det_le0 = (long long)res[1];
+    out->trace_ge95 = (long long)res[2];
+    out->max_div = res[3];
+    out->energy = res[4];
+    return EVP_OK;
+}
+
+namespace {
+
+struct StateHeader {
+    long long magic, nx, ny, nz, bc, precision, have_hist, nstep;
+};
+constexpr long long kStateMagic = 0x45565053544154ALL;   // "EVPSTAT"
+
+size_t state_field_bytes(const evp_grid* g)
+{
+    const Layout& L = g->L;
+    // u, v, w, us, vs, ws, p are contiguous; then the current B, RT, RU
+    return (L.B0 - L.u) + (L.B1 - L.B0) + (L.spec - L.RT);
+}
+
+}  // namespace
+
+size_t evp_state_bytes(const evp_grid* g)
+{
+    if (!g) return 0;
+    return 256 + state_field_bytes(g);
+}
+
+int evp_save_state(evp_grid* g, void* dst, size_t bytes)
+{
+    if (int r = check_grid(g)) return r;
+    if (!dst || reinterpret_cast<uintptr_t>(dst) % kAlign) return fail(EVP_ERR_ARG, "dst must be 256-byte aligned");
+    if (bytes < evp_state_bytes(g)) return fail(EVP_ERR_WORKSPACE, "state buffer too small");
+    const Layout& L = g->L;
+    char* d = reinterpret_cast<char*>(dst);
+    StateHeader hd{kStateMagic, g->nx, g->ny, g->nz, g->bc, g->precision, g->have_hist ? 1 : 0, g->nstep};
+    hipError_t e = hipMemcpyAsync(d, &hd, sizeof hd, hipMemcpyHostToDevice, g->stream);
+    size_t o = 256;
+    const char* B = g->ws + (g->parity ? L.B1 : L.B0);
+    if (e == hipSuccess) e = hipMemcpyAsync(d + o, g->ws + L.u, L.B0 - L.u, hipMemcpyDeviceToDevice, g->stream);
+    o += L.B0 - L.u;
+    if (e == hipSuccess) e = hipMemcpyAsync(d + o, B, L.B1 - L.B0, hipMemcpyDeviceToDevice, g->stream);
+    o += L.B1 - L.B0;
+    if (e == hipSuccess) e = hipMemcpyAsync(d + o, g->ws + L.RT, L.spec - L.RT, hipMemcpyDeviceToDevice, g->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+    if (e != hipSuccess) return hip_fail(e, "save_state");
+    return EVP_OK;
+}
+
+int evp_load_state(evp_grid* g, const void* src, size_t bytes)
+{
+    if (int r = check_grid(g)) return r;
+    if (!src || reinterpret_cast<uintptr_t>(src) % kAlign) return fail(EVP_ERR_ARG, "src must be 256-byte aligned");
+    if (bytes < evp_state_bytes(g)) return fail(EVP_ERR_WORKSPACE, "state buffer too small");
+    const Layout& L = g->L;
+    const char* s = reinterpret_cast<const char*>(src);
+    StateHeader hd{};
+    hipError_t e = hipMemcpyAsync(&hd, s, sizeof hd, hipMemcpyDeviceToHost, g->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+    if (e != hipSuccess) return hip_fail(e, "load_state header");
+    if (hd.magic != kStateMagic || hd.nx != g->nx || hd.ny != g->ny || hd.nz != g->nz || hd.bc != g->bc ||
+        hd.precision != g->precision)
+        return fail(EVP_ERR_SHAPE, "state was saved from a grid of another shape, boundary type or precision");
+    size_t o = 256;
+    e = hipMemcpyAsync(g->ws + L.u, s + o, L.B0 - L.u, hipMemcpyDeviceToDevice, g->stream);
+    o += L.B0 - L.u;
+    if (e == hipSuccess) e = hipMemcpyAsync(g->ws + (g->parity ? L.B1 : L.B0), s + o, L.B1 - L.B0, hipMemcpyDeviceToDevice, g->stream);
+    o += L.B1 - L.B0;
+    if (e == hipSuccess) e = hipMemcpyAsync(g->ws + L.RT, s + o, L.spec - L.RT, hipMemcpyDeviceToDevice, g->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+    if (e != hipSuccess) return hip_fail(e, "load_state");
+    g->have_hist = hd.have_hist != 0;
+    g->nstep = hd.nstep;
+    g->have_fields = true;
+    return EVP_OK;
+}
+
+int evp_step_count(evp_grid* g, long long* out)
+{
+    if (int r = check_grid(g)) return r;
+    if (!out) return fail(EVP_ERR_ARG, "out is NULL");
+    *out = g->nstep;
+    return EVP_OK;
+}
+
+int evp_profile(evp_grid* g, int enable)
+{
+    if (int r = check_grid(g)) return r;
+    if (enable) {
+        fold_events(g);
+        for (int k = 0; k < EVP_K_COUNT; ++k) { g->prof_ms[k] = 0.0; g->prof_launches[k] = 0; }
+    }
+    g->prof = enable != 0;
+    return EVP_OK;
+}
+
+int evp_profile_read(evp_grid* g, evp_profile_t* out)
+{
+    if (int r = check_grid(g)) return r;
+    if (!out) return fail(EVP_ERR_ARG, "out is NULL");
+    hipError_t e = hipStreamSynchronize(g->stream);
+    if (e != hipSuccess) return hip_fail(e, "profile sync");
+    fold_events(g);
+    for (int k = 0; k < EVP_K_COUNT; ++k) { out->ms[k] = g->prof_ms[k]; out->launches[k] = g->prof_launches[k]; }
+    return EVP_OK;
+}
+
+int evp_destroy_grid(evp_grid* g)
+{
+    if (!g) return EVP_OK;
+    if (!g->pending.empty()) {
+        (void)hipStreamSynchronize(g->stream);
+        fold_events(g);
+    }
+    for (hipEvent_t e : g->free_events) (void)hipEventDestroy(e);
+    delete g;
+    return EVP_OK;
+}
+
+}  // extern "C"

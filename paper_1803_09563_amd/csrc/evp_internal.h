@@ -1,0 +1,73 @@
+// Internal declarations of libevp.so: the per-grid device descriptor, the batch argument block
+// passed by value to every kernel, and the host-side launchers of each kernel family.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+
+#include "../../include/evp.h"
+
+namespace evp {
+
+// Per-grid constants and pointers.  Lives at the start of the grid's workspace (device) and is
+// mirrored in the host-side grid; kernels read it through a uniform pointer (scalar loads).
+struct Desc {
+    int nx, ny, nz, nh;          // cells; nh = nx/2 + 1 complex values per x-spectrum line
+    int walls;                   // EVP_WALLS in y?
+    int precision;               // EVP_FP64 or EVP_MIXED
+    int model;                   // EVP_OLDROYD_B / EVP_FENE_P / EVP_SARAMITO
+    int force_kind;              // EVP_FORCE_*
+    long long ncell;             // nx*ny*nz
+    long long ps;                // element stride between planes of B, RT, RU (256-byte padded)
+    double dx, dy, dz, idx, idy, idz, y0;
+    double rho, inv_rho, mu_s, mu_p, lam, inv_lam, G, tau_y, L2, a_fene;
+    double force_amp, force_ky;
+    double u_bot, u_top, w_bot, w_top;
+    double *u, *v, *w;           // velocity u^n (FP64)
+    double *us, *vs, *ws;        // predicted velocity u* (FP64)
+    void* Bt[2];                 // B - I, six planes each, ping-pong (double or float)
+    void* RT;                    // stress right-hand side history, six planes (double or float)
+    void* RU;                    // momentum right-hand side history, three planes
+    double* p;                   // pressure
+    double2* spec;               // half spectrum [nz][ny][nh]
+    const double2 *twx, *twy, *twz;        // W_N^n = exp(-2 pi i n / N), n < N, per direction
+    const double *eigx, *eigy, *eigz;      // -(4/h^2) sin^2(pi k / N) per direction
+    const double* piv;           // walls: Thomas pivots 1/(b_j - a c'_{j-1}) [nz/2+1][ny][nh]
+    double* red;                 // reduction partials (health)
+};
+
+// Argument block of every batched kernel (by value; < 1 KiB).
+struct Batch {
+    const Desc* d[EVP_MAX_BATCH];
+    double dt[EVP_MAX_BATCH];
+    int state[EVP_MAX_BATCH];    // bit 0: index of the current B buffer; bit 1: no AB2 history
+    int count;
+};
+
+constexpr int ST_PARITY = 1;
+constexpr int ST_EULER = 2;
+
+// Host-side launchers (one per kernel family); shape is common to the whole batch.
+hipError_t launch_predictor(const Batch& b, int precision, int nx, int ny, int nz, bool freeze,
+                            hipStream_t s);
+hipError_t launch_div_fftx(const Batch& b, int nx, int ny, int nz, hipStream_t s);
+hipError_t launch_fft_strided(const Batch& b, int nx, int ny, int nz, int axis, bool inverse,
+                              hipStream_t s);
+hipError_t launch_solve_periodic(const Batch& b, int nx, int ny, int nz, hipStream_t s);
+hipError_t launch_thomas(const Batch& b, int nx, int ny, int nz, hipStream_t s);
+hipError_t launch_ifftx(const Batch& b, int nx, int ny, int nz, hipStream_t s);
+hipError_t launch_correct(const Batch& b, int nx, int ny, int nz, hipStream_t s);
+hipError_t launch_copy_ustar(const Batch& b, int nx, int ny, int nz, bool to_u, hipStream_t s);
+hipError_t launch_write_fields(const Desc* d, int precision, long long ncell, int ny, int nx,
+                               int walls, int parity, const double* u, const double* v,
+                               const double* w, const double* B6, const double* hist,
+                               hipStream_t s);
+hipError_t launch_read_fields(const Desc* d, int precision, long long ncell, int parity,
+                              unsigned mask, double* u, double* v, double* w, double* p,
+                              double* B6, double* hist, hipStream_t s);
+hipError_t launch_health(const Desc* d, int precision, int nx, int ny, int nz, int parity,
+                         double* partial_host_result, hipStream_t s);
+
+bool fft_size_supported(int n);
+
+}  // namespace evp

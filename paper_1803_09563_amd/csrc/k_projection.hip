@@ -1,0 +1,407 @@
+// Pressure projection, Sec. 3.2.2 Eqs. (var poisson) and (projection) with constant rho:
+//   r = rho (D_h u*) / dt;  L_h p = r (zero-mean p);  u^{n+1} = u* - (dt/rho) G_h p.
+// The 7-point Laplacian L_h = D_h G_h is diagonalised by discrete Fourier transforms in periodic
+// directions (eigenvalues -(4/h^2) sin^2(pi k/N)); across walls (homogeneous Neumann rows) each
+// (kx, kz) mode is a tridiagonal system in y solved by a Thomas sweep.
+//
+// Passes over the half spectrum S[kz][j][kx] (kx < nx/2+1, FP64 complex):
+//   periodic: div+fft(x) | fft(y) | fft(z), divide, ifft(z) | ifft(y) | ifft(x) -> p | correct
+//   walls:    div+fft(x) | fft(z) | Thomas(y)                | ifft(z) | ifft(x) -> p | correct
+// Real x-lines are transformed two at a time as one complex line (a + i b).
+#include "evp_internal.h"
+#include "fft_lds.h"
+
+namespace evp {
+
+namespace {
+
+constexpr int NT = 256;    // threads per block of the line-transform kernels
+constexpr int TK = 16;     // consecutive kx per block in the strided passes
+
+__device__ __forceinline__ int wrapi(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+// ---------------------------------------------------------------------------------------------
+// div + forward x transform
+// ---------------------------------------------------------------------------------------------
+template <int N>
+__global__ __launch_bounds__(NT) void k_div_fftx(Batch B)
+{
+    constexpr int T = fft_threads<N>();
+    constexpr int LP = NT / T;                 // complex lines (= real line pairs) per block
+    constexpr int NHF = N / 2 + 1;
+    __shared__ double2 buf[LP * N];
+    __shared__ double2 tw[N];
+    const Desc& D = *B.d[blockIdx.y];
+    const double sc = D.rho / B.dt[blockIdx.y];
+    const int tid = threadIdx.x;
+    for (int n = tid; n < N; n += NT) tw[n] = D.twx[n];
+    const int ny = D.ny, nz = D.nz;
+    const int nlines = ny * nz;
+    const int npairs = (nlines + 1) >> 1;
+    const int pair0 = blockIdx.x * LP;
+    const double idx = D.idx, idy = D.idy, idz = D.idz;
+    const long long sxy = (long long)N * ny;
+    for (int e = tid; e < LP * N; e += NT) {
+        const int lp = e / N, i = e - lp * N;
+        const int pair = pair0 + lp;
+        double r2[2] = {0.0, 0.0};
+        if (pair < npairs) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int l = 2 * pair + h;
+                if (l < nlines) {
+                    const int k = l / ny, j = l - k * ny;
+                    const long long q = (long long)l * N + i;
+                    const double du = D.us[q] - D.us[q - i + wrapi(i - 1, N)];
+                    double vm;
+                    if (j > 0) vm = D.vs[q - N];
+                    else vm = D.walls ? 0.0 : D.vs[q + (long long)(ny - 1) * N];
+                    const double dv = D.vs[q] - vm;
+                    const double wm = (k > 0) ? D.ws[q - sxy] : D.ws[q + (long long)(nz - 1) * sxy];
+                    const double dw = D.ws[q] - wm;
+                    r2[h] = sc * (du * idx + dv * idy + dw * idz);
+                }
+            }
+        }
+        buf[lp * N + i] = make_double2(r2[0], r2[1]);
+    }
+    __syncthreads();
+    const int lp = tid / T, t = tid - (tid / T) * T;
+    fft_stages<N, T, 0, 1>(buf + lp * N, 1, t, lp < LP, tw);
+    const int nh = D.nh;
+    for (int e = tid; e < LP * NHF; e += NT) {
+        const int l2 = e / NHF, k = e - l2 * NHF;
+        const int pair = pair0 + l2;
+        if (pair >= npairs) continue;
+        const double2 Z = buf[l2 * N + k];
+        const double2 Zc = cconj(buf[l2 * N + (k == 0 ? 0 : N - k)]);
+        const double2 s = cadd(Z, Zc), d = csub(Z, Zc);
+        const int la = 2 * pair;
+        D.spec[(long long)la * nh + k] = make_double2(0.5 * s.x, 0.5 * s.y);
+        if (la + 1 < nlines)
+            D.spec[(long long)(la + 1) * nh + k] = make_double2(0.5 * d.y, -0.5 * d.x);
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// strided forward / inverse transform along y (axis 1) or z (axis 2), in place
+// ---------------------------------------------------------------------------------------------
+template <int N>
+constexpr int strided_threads() { return fft_threads<N>() < NT / TK ? fft_threads<N>() : NT / TK; }
+
+template <int N, bool INV>
+__global__ __launch_bounds__(NT) void k_fft_strided(Batch B, int axis)
+{
+    constexpr int T = strided_threads<N>();
+    __shared__ double2 buf[N * TK];
+    __shared__ double2 tw[N];
+    const Desc& D = *B.d[blockIdx.y];
+    const int tid = threadIdx.x;
+    const double2* twg = axis == 1 ? D.twy : D.twz;
+    for (int n = tid; n < N; n += NT) tw[n] = twg[n];
+    const int nh = D.nh, ny = D.ny;
+    const int ntk = (nh + TK - 1) / TK;
+    const int tile = blockIdx.x % ntk, other = blockIdx.x / ntk;
+    const int kx0 = tile * TK;
+    long long base, es;
+    if (axis == 1) { base = (long long)other * ny * nh + kx0; es = nh; }
+    else { base = (long long)other * nh + kx0; es = (long long)nh * ny; }
+    for (int e = tid; e < N * TK; e += NT) {
+        const int n = e / TK, c = e - n * TK;
+        double2 x = make_double2(0.0, 0.0);
+        if (kx0 + c < nh) x = D.spec[base + n * es + c];
+        buf[e] = INV ? cconj(x) : x;
+    }
+    __syncthreads();
+    const int c = tid % TK, t = tid / TK;
+    fft_stages<N, T, 0, 1>(buf + c, TK, t, t < T, tw);
+    for (int e = tid; e < N * TK; e += NT) {
+        const int n = e / TK, cc = e - n * TK;
+        if (kx0 + cc < nh) {
+            const double2 x = buf[e];
+            D.spec[base + n * es + cc] = INV ? cconj(x) : x;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// periodic: transform along z, divide by the Laplacian eigenvalue, transform back (in place)
+// ---------------------------------------------------------------------------------------------
+template <int N>
+__global__ __launch_bounds__(NT) void k_solve_periodic(Batch B)
+{
+    constexpr int T = strided_threads<N>();
+    __shared__ double2 buf[N * TK];
+    __shared__ double2 tw[N];
+    const Desc& D = *B.d[blockIdx.y];
+    const int tid = threadIdx.x;
+    for (int n = tid; n < N; n += NT) tw[n] = D.twz[n];
+    const int nh = D.nh, ny = D.ny;
+    const int ntk = (nh + TK - 1) / TK;
+    const int tile = blockIdx.x % ntk, ky = blockIdx.x / ntk;
+    const int kx0 = tile * TK;
+    const long long base = (long long)ky * nh + kx0, es = (long long)nh * ny;
+    for (int e = tid; e < N * TK; e += NT) {
+        const int n = e / TK, c = e - n * TK;
+        buf[e] = (kx0 + c < nh) ? D.spec[base + n * es + c] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    const int c = tid % TK, t = tid / TK;
+    fft_stages<N, T, 0, 1>(buf + c, TK, t, t < T, tw);
+    const double scale = 1.0 / ((double)D.nx * ny * N);
+    const double ey = D.eigy[ky];
+    for (int e = tid; e < N * TK; e += NT) {
+        const int kz = e / TK, cc = e - kz * TK;
+        const int kx = kx0 + cc;
+        double2 x = buf[e];
+        if (kx < nh) {
+            const double den = D.eigx[kx] + ey + D.eigz[kz];
+            const double f = (kx == 0 && ky == 0 && kz == 0) ? 0.0 : scale / den;
+            x = cscale(x, f);
+        }
+        buf[e] = cconj(x);        // inverse transform by conjugation
+    }
+    __syncthreads();
+    fft_stages<N, T, 0, 1>(buf + c, TK, t, t < T, tw);
+    for (int e = tid; e < N * TK; e += NT) {
+        const int n = e / TK, cc = e - n * TK;
+        if (kx0 + cc < nh) D.spec[base + n * es + cc] = cconj(buf[e]);
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// walls: tridiagonal solve in y for every (kx, kz), pivots precomputed per (kx, |kz|)
+// ---------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_thomas(Batch B)
+{
+    const Desc& D = *B.d[blockIdx.y];
+    const int nh = D.nh, ny = D.ny, nz = D.nz;
+    const int col = blockIdx.x * 256 + threadIdx.x;
+    if (col >= nh * nz) return;
+    const int kz = col / nh, kx = col - kz * nh;
+    const int kzs = kz <= nz - kz ? kz : nz - kz;
+    const double* piv = D.piv + (long long)kzs * ny * nh + kx;
+    double2* s = D.spec + (long long)kz * ny * nh + kx;
+    const double a = D.idy * D.idy;                  // sub- and super-diagonal 1/dy^2
+    const double scale = 1.0 / ((double)D.nx * nz);  // inverse x and z transforms
+    double2 dp = make_double2(0.0, 0.0);
+    for (int j = 0; j < ny; ++j) {
+        const double2 r = s[(long long)j * nh];
+        const double iv = piv[(long long)j * nh];
+        dp = make_double2((scale * r.x - a * dp.x) * iv, (scale * r.y - a * dp.y) * iv);
+        s[(long long)j * nh] = dp;
+    }
+    double2 x = dp;
+    for (int j = ny - 2; j >= 0; --j) {
+        const double2 d = s[(long long)j * nh];
+        const double cp = a * piv[(long long)j * nh];
+        x = make_double2(d.x - cp * x.x, d.y - cp * x.y);
+        s[(long long)j * nh] = x;
+    }
+    if (kx == 0 && kz == 0) {
+        // gauge: zero volume mean of p is zero mean of the (0,0) mode over y
+        double sum = 0.0;
+        for (int j = 0; j < ny; ++j) sum += s[(long long)j * nh].x;
+        const double m = sum / ny;
+        for (int j = 0; j < ny; ++j) {
+            double2 v = s[(long long)j * nh];
+            s[(long long)j * nh] = make_double2(v.x - m, v.y);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// inverse x transform of two half spectra -> two real lines of p
+// ---------------------------------------------------------------------------------------------
+template <int N>
+__global__ __launch_bounds__(NT) void k_ifftx(Batch B)
+{
+    constexpr int T = fft_threads<N>();
+    constexpr int LP = NT / T;
+    __shared__ double2 buf[LP * N];
+    __shared__ double2 tw[N];
+    const Desc& D = *B.d[blockIdx.y];
+    const int tid = threadIdx.x;
+    for (int n = tid; n < N; n += NT) tw[n] = D.twx[n];
+    const int nlines = D.ny * D.nz;
+    const int npairs = (nlines + 1) >> 1;
+    const int pair0 = blockIdx.x * LP;
+    const int nh = D.nh;
+    for (int e = tid; e < LP * N; e += NT) {
+        const int lp = e / N, n = e - lp * N;
+        const int pair = pair0 + lp;
+        double2 Z = make_double2(0.0, 0.0);
+        if (pair < npairs) {
+            const int la = 2 * pair;
+            const bool hasb = la + 1 < nlines;
+            const bool lo = n <= N / 2;
+            const int k = lo ? n : N - n;
+            double2 a = D.spec[(long long)la * nh + k];
+            double2 b = hasb ? D.spec[(long long)(la + 1) * nh + k] : make_double2(0.0, 0.0);
+            if (!lo) { a = cconj(a); b = cconj(b); }
+            Z = make_double2(a.x - b.y, a.y + b.x);   // a + i b
+        }
+        buf[e] = cconj(Z);
+    }
+    __syncthreads();
+    const int lp = tid / T, t = tid - (tid / T) * T;
+    fft_stages<N, T, 0, 1>(buf + lp * N, 1, t, lp < LP, tw);
+    for (int e = tid; e < LP * N; e += NT) {
+        const int l2 = e / N, n = e - l2 * N;
+        const int pair = pair0 + l2;
+        if (pair >= npairs) continue;
+        const double2 z = cconj(buf[e]);
+        const int la = 2 * pair;
+        D.p[(long long)la * N + n] = z.x;
+        if (la + 1 < nlines) D.p[(long long)(la + 1) * N + n] = z.y;
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// velocity correction u = u* - (dt/rho) G_h p; copies between u and u*
+// ---------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_correct(Batch B)
+{
+    const Desc& D = *B.d[blockIdx.y];
+    const int nx = D.nx, ny = D.ny, nz = D.nz;
+    const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (q >= D.ncell) return;
+    const int i = (int)(q % nx);
+    const long long r = q / nx;
+    const int j = (int)(r % ny), k = (int)(r / ny);
+    const double c = B.dt[blockIdx.y] * D.inv_rho;
+    const double p0 = D.p[q];
+    const double px = D.p[q - i + (i + 1 == nx ? 0 : i + 1)];
+    const long long sxy = (long long)nx * ny;
+    const double pz = D.p[k + 1 == nz ? q - (long long)(nz - 1) * sxy : q + sxy];
+    D.u[q] = D.us[q] - c * (px - p0) * D.idx;
+    D.w[q] = D.ws[q] - c * (pz - p0) * D.idz;
+    if (j + 1 == ny) {
+        D.v[q] = D.walls ? 0.0 : D.vs[q] - c * (D.p[q - (long long)(ny - 1) * nx] - p0) * D.idy;
+    } else {
+        D.v[q] = D.vs[q] - c * (D.p[q + nx] - p0) * D.idy;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_copy_ustar(Batch B, int to_u)
+{
+    const Desc& D = *B.d[blockIdx.y];
+    const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (q >= D.ncell) return;
+    if (to_u) { D.u[q] = D.us[q]; D.v[q] = D.vs[q]; D.w[q] = D.ws[q]; }
+    else { D.us[q] = D.u[q]; D.vs[q] = D.v[q]; D.ws[q] = D.w[q]; }
+}
+
+}  // namespace
+
+bool fft_size_supported(int n)
+{
+    switch (n) {
+    case 8: case 12: case 16: case 24: case 32: case 48: case 64: case 96: case 128: case 192:
+    case 256: case 384: case 512:
+        return true;
+    default:
+        return false;
+    }
+}
+
+#define EVP_FFT_SWITCH(n, CALL)                                                                  \
+    switch (n) {                                                                                 \
+    case 8: CALL(8); break;                                                                      \
+    case 12: CALL(12); break;                                                                    \
+    case 16: CALL(16); break;                                                                    \
+    case 24: CALL(24); break;                                                                    \
+    case 32: CALL(32); break;                                                                    \
+    case 48: CALL(48); break;                                                                    \
+    case 64: CALL(64); break;                                                                    \
+    case 96: CALL(96); break;                                                                    \
+    case 128: CALL(128); break;                                                                  \
+    case 192: CALL(192); break;                                                                  \
+    case 256: CALL(256); break;                                                                  \
+    case 384: CALL(384); break;                                                                  \
+    case 512: CALL(512); break;                                                                  \
+    default: return hipErrorInvalidValue;                                                        \
+    }
+
+hipError_t launch_div_fftx(const Batch& b, int nx, int ny, int nz, hipStream_t s)
+{
+    const int npairs = (ny * nz + 1) / 2;
+#define CALL(N)                                                                                  \
+    {                                                                                            \
+        constexpr int LP = NT / fft_threads<N>();                                                \
+        dim3 grid((npairs + LP - 1) / LP, b.count);                                              \
+        hipLaunchKernelGGL(k_div_fftx<N>, grid, dim3(NT), 0, s, b);                              \
+    }
+    EVP_FFT_SWITCH(nx, CALL)
+#undef CALL
+    return hipGetLastError();
+}
+
+hipError_t launch_ifftx(const Batch& b, int nx, int ny, int nz, hipStream_t s)
+{
+    const int npairs = (ny * nz + 1) / 2;
+#define CALL(N)                                                                                  \
+    {                                                                                            \
+        constexpr int LP = NT / fft_threads<N>();                                                \
+        dim3 grid((npairs + LP - 1) / LP, b.count);                                              \
+        hipLaunchKernelGGL(k_ifftx<N>, grid, dim3(NT), 0, s, b);                                 \
+    }
+    EVP_FFT_SWITCH(nx, CALL)
+#undef CALL
+    return hipGetLastError();
+}
+
+hipError_t launch_fft_strided(const Batch& b, int nx, int ny, int nz, int axis, bool inverse,
+                              hipStream_t s)
+{
+    const int nh = nx / 2 + 1;
+    const int ntk = (nh + TK - 1) / TK;
+    const int n = axis == 1 ? ny : nz;
+    const int other = axis == 1 ? nz : ny;
+    dim3 grid(ntk * other, b.count);
+#define CALL(N)                                                                                  \
+    {                                                                                            \
+        if (inverse) hipLaunchKernelGGL((k_fft_strided<N, true>), grid, dim3(NT), 0, s, b, axis); \
+        else hipLaunchKernelGGL((k_fft_strided<N, false>), grid, dim3(NT), 0, s, b, axis);       \
+    }
+    EVP_FFT_SWITCH(n, CALL)
+#undef CALL
+    return hipGetLastError();
+}
+
+hipError_t launch_solve_periodic(const Batch& b, int nx, int ny, int nz, hipStream_t s)
+{
+    const int nh = nx / 2 + 1;
+    const int ntk = (nh + TK - 1) / TK;
+    dim3 grid(ntk * ny, b.count);
+#define CALL(N) hipLaunchKernelGGL(k_solve_periodic<N>, grid, dim3(NT), 0, s, b);
+    EVP_FFT_SWITCH(nz, CALL)
+#undef CALL
+    return hipGetLastError();
+}
+
+hipError_t launch_thomas(const Batch& b, int nx, int ny, int nz, hipStream_t s)
+{
+    const int cols = (nx / 2 + 1) * nz;
+    dim3 grid((cols + 255) / 256, b.count);
+    hipLaunchKernelGGL(k_thomas, grid, dim3(256), 0, s, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_correct(const Batch& b, int nx, int ny, int nz, hipStream_t s)
+{
+    const long long n = (long long)nx * ny * nz;
+    dim3 grid((unsigned)((n + 255) / 256), b.count);
+    hipLaunchKernelGGL(k_correct, grid, dim3(256), 0, s, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_ustar(const Batch& b, int nx, int ny, int nz, bool to_u, hipStream_t s)
+{
+    const long long n = (long long)nx * ny * nz;
+    dim3 grid((unsigned)((n + 255) / 256), b.count);
+    hipLaunchKernelGGL(k_copy_ustar, grid, dim3(256), 0, s, b, to_u ? 1 : 0);
+    return hipGetLastError();
+}
+
+}  // namespace evp

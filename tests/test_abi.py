@@ -1,0 +1,84 @@
+"""The C-ABI library loads and exports every entry point include/evp.h declares; host-only paths
+(workspace sizing, argument validation, error strings) behave as documented.  No GPU needed."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1803_09563_amd as evp
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "evp.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(evp_[a-z_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    names = _declared()
+    assert len(names) >= 18
+    for n in names:
+        assert hasattr(evp.lib, n), n
+    assert set(names) == set(evp.symbols)
+
+
+def test_workspace_bytes_valid_and_invalid_shapes():
+    a = evp.workspace_bytes(32, 32, 32)
+    b = evp.workspace_bytes(32, 32, 32, precision=evp.MIXED)
+    c = evp.workspace_bytes(64, 48, 32, walls=True)
+    assert a > 28 * 8 * 32 ** 3 and b < a and c > 0
+    assert evp.workspace_bytes(30, 32, 32) == 0          # 30 = 2*3*5: radix 5 unsupported
+    assert evp.workspace_bytes(31, 32, 32) == 0          # odd nx
+    assert evp.workspace_bytes(32, 20, 32) == 0          # periodic y needs an FFT size
+    assert evp.workspace_bytes(32, 20, 32, walls=True) > 0
+    assert evp.workspace_bytes(32, 3, 32, walls=True) == 0
+    assert evp.workspace_bytes(32, 32, 32, precision=7) == 0
+
+
+def test_workspace_covers_the_state():
+    """FP64: 7 velocity/pressure fields, 21 stress/history planes, the half spectrum."""
+    nx, ny, nz = 128, 128, 128
+    n = nx * ny * nz
+    need = 8 * n * (7 + 21) + 16 * (nx // 2 + 1) * ny * nz
+    got = evp.workspace_bytes(nx, ny, nz)
+    assert need <= got < need * 1.01
+
+
+def test_error_strings_and_argument_errors():
+    assert evp.lib.evp_error_string(0) == b"ok"
+    assert evp.lib.evp_error_string(-2).startswith(b"workspace")
+    h = ctypes.c_void_p()
+    # invalid shape is rejected before any device call
+    st = evp.lib.evp_create_grid(30, 32, 32, 1.0, 1.0, 1.0, 0, 0, ctypes.c_void_p(256), 1 << 30,
+                                 None, ctypes.byref(h))
+    assert st == -1 and b"nx=30" in evp.lib.evp_last_error()
+    st = evp.lib.evp_create_grid(32, 32, 32, 1.0, 1.0, 1.0, 0, 0, None, 1 << 30, None,
+                                 ctypes.byref(h))
+    assert st == -2
+    st = evp.lib.evp_create_grid(32, 32, 32, 1.0, 1.0, 1.0, 0, 0, ctypes.c_void_p(4096 + 8),
+                                 1 << 30, None, ctypes.byref(h))
+    assert st == -2 and b"aligned" in evp.lib.evp_last_error()
+    st = evp.lib.evp_create_grid(32, 32, 32, 1.0, 1.0, 1.0, 0, 0, ctypes.c_void_p(4096), 1024,
+                                 None, ctypes.byref(h))
+    assert st == -2 and b"needs" in evp.lib.evp_last_error()
+    st = evp.lib.evp_create_grid(32, 32, 32, -1.0, 1.0, 1.0, 0, 0, ctypes.c_void_p(4096),
+                                 1 << 30, None, ctypes.byref(h))
+    assert st == -1
+    assert evp.lib.evp_step(None, 1e-3, 1, 0) == -1
+    assert evp.lib.evp_destroy_grid(None) == 0
+    arr = (ctypes.c_void_p * 1)(None)
+    assert evp.lib.evp_step_batch(arr, 0, 1e-3, 1, 0) == -1
+    assert evp.lib.evp_step_batch(arr, 1, 1e-3, 1, 0) == -1
+
+
+def test_no_cpu_fallback_in_package():
+    """The package path never imports the oracle or numpy-based solvers."""
+    pkg = os.path.join(ROOT, "paper_1803_09563_amd")
+    for fn in os.listdir(pkg):
+        if fn.endswith(".py"):
+            src = open(os.path.join(pkg, fn)).read()
+            assert "import oracle" not in src and "from oracle" not in src, fn
