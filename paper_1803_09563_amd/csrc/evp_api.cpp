@@ -4,6 +4,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -251,6 +252,16 @@ void build_tables(const evp_grid* g, std::vector<char>& host, size_t base)
     }
 }
 
+// EVP_PREDICTOR=ref selects the per-cell reference predictor (A/B checks); default: z-marching
+bool use_reference_predictor()
+{
+    static const bool ref = [] {
+        const char* e = std::getenv("EVP_PREDICTOR");
+        return e && std::strcmp(e, "ref") == 0;
+    }();
+    return ref;
+}
+
 int check_grid(evp_grid* g)
 {
     if (!g) return fail(EVP_ERR_ARG, "null grid");
@@ -271,7 +282,10 @@ int enqueue_steps(evp_grid* const* gs, int count, double dt, int nsteps, unsigne
             b.state[i] = gs[i]->parity | (gs[i]->have_hist ? 0 : evp::ST_EULER);
         }
         int r = timed(g0, EVP_K_PREDICTOR, [&] {
-            return evp::launch_predictor(b, g0->precision, g0->nx, g0->ny, g0->nz, freeze, g0->stream);
+            return use_reference_predictor()
+                       ? evp::launch_predictor_ref(b, g0->precision, g0->nx, g0->ny, g0->nz, freeze, g0->stream)
+                       : evp::launch_predictor_zm(b, g0->precision, g0->nx, g0->ny, g0->nz, freeze, g0->stream,
+                                                  g0->bc == EVP_WALLS);
         });
         if (r) return r;
         if (stop && !freeze) {

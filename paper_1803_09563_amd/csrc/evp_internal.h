@@ -48,8 +48,11 @@ constexpr int ST_PARITY = 1;
 constexpr int ST_EULER = 2;
 
 // Host-side launchers (one per kernel family); shape is common to the whole batch.
-hipError_t launch_predictor(const Batch& b, int precision, int nx, int ny, int nz, bool freeze,
-                            hipStream_t s);
+hipError_t launch_predictor_ref(const Batch& b, int precision, int nx, int ny, int nz, bool freeze,
+                                hipStream_t s);
+hipError_t launch_predictor_zm(const Batch& b, int precision, int nx, int ny, int nz, bool freeze,
+                               hipStream_t s, bool walls);
+int predictor_chunk(int nx, int ny, int nz);
 hipError_t launch_div_fftx(const Batch& b, int nx, int ny, int nz, hipStream_t s);
 hipError_t launch_fft_strided(const Batch& b, int nx, int ny, int nz, int axis, bool inverse,
                               hipStream_t s);

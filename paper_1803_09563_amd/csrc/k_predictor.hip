@@ -321,8 +321,8 @@ __global__ __launch_bounds__(BX * BY) void k_predictor(Batch B, int freeze)
 
 }  // namespace
 
-hipError_t launch_predictor(const Batch& b, int precision, int nx, int ny, int nz, bool freeze,
-                            hipStream_t s)
+hipError_t launch_predictor_ref(const Batch& b, int precision, int nx, int ny, int nz, bool freeze,
+                                hipStream_t s)
 {
     dim3 block(BX, BY);
     dim3 grid((nx + BX - 1) / BX, ((ny + BY - 1) / BY) * nz, b.count);

@@ -1,0 +1,449 @@
+// Predictor of the Adams-Bashforth step (Sec. 3.2.2, Eqs. (rt), (ab2tau), (ru), (ab2)) as a
+// z-marching LDS-tiled kernel.  Same arithmetic as the per-cell kernel in k_predictor.hip, laid
+// out for CDNA4:
+//   * a block of 32 x 8 threads owns a 32 x 8 column of cells and marches along z over a chunk of
+//     planes, so every field is read from HBM about once;
+//   * the seven planes k-3..k+3 that the z-direction WENO needs for the thread's own cell live in
+//     registers (a sliding window);
+//   * plane k of B - I, with the 3-cell cross halo of the x/y WENO stencils (ghost rows beyond a
+//     wall extrapolated at load time), sits in LDS;
+//   * three-plane rings in LDS hold the velocities and the stress components tau_xz, tau_yz,
+//     tau_zz of planes k-1, k, k+1 on the tile plus a 1-cell halo (momentum stencils and the
+//     velocity gradient);
+//   * FENE-P stress factors G F and G (F - a) of plane k are staged once per cell.
+// Block ids are remapped so consecutive tiles land on the same XCD (shared L2 for halo reads).
+#include <cstdlib>
+
+#include "evp_internal.h"
+
+namespace evp {
+
+namespace {
+
+constexpr int TX = 32, TY = 8, NTH = TX * TY;
+constexpr int RW = TX + 6, RH = TY + 6;    // B plane with a 3-cell halo
+constexpr int BW = TX + 2, BH = TY + 2;    // 1-cell halo box
+constexpr int BOX = BW * BH;
+
+__device__ __forceinline__ int modp(int i, int n)
+{
+    int r = i % n;
+    return r < 0 ? r + n : r;
+}
+
+template <typename T> struct Smem {
+    T B[6][RH][RW];      // B - I of plane k
+    T gf[BH][BW];        // G F of plane k (G for Oldroyd-B / Saramito)
+    T ga[BH][BW];        // G (F - a) of plane k (0 for Oldroyd-B / Saramito)
+    T Z[3][3][BH][BW];   // ring slot, (tau_xz, tau_yz, tau_zz)
+    T V[3][3][BH][BW];   // ring slot, (u, v, w)
+};
+
+// reciprocal to full precision: hardware estimate refined by Newton steps (x <- x (2 - a x))
+__device__ __forceinline__ double fast_rcp(double a)
+{
+    double x = __builtin_amdgcn_rcp(a);
+    x = fma(x, fma(-a, x, 1.0), x);
+    x = fma(x, fma(-a, x, 1.0), x);
+    return x;
+}
+__device__ __forceinline__ float fast_rcp(float a)
+{
+    float x = __builtin_amdgcn_rcpf(a);
+    return fmaf(x, fmaf(-a, x, 1.0f), x);
+}
+
+// Fifth-order WENO from the five undivided one-sided differences e1..e5 (spacing folded out):
+// returns h * dB/dx.  eps2 = eps h^2 keeps the weights equal to those of the divided form.
+template <typename T>
+__device__ __forceinline__ T weno5u(T v1, T v2, T v3, T v4, T v5, T eps2)
+{
+    const T c13 = (T)(13.0 / 12.0), q = (T)0.25;
+    const T p1 = v1 * (T)(1.0 / 3.0) - v2 * (T)(7.0 / 6.0) + v3 * (T)(11.0 / 6.0);
+    const T p2 = -v2 * (T)(1.0 / 6.0) + v3 * (T)(5.0 / 6.0) + v4 * (T)(1.0 / 3.0);
+    const T p3 = v3 * (T)(1.0 / 3.0) + v4 * (T)(5.0 / 6.0) - v5 * (T)(1.0 / 6.0);
+    T a = v1 - (T)2 * v2 + v3, b = v1 - (T)4 * v2 + (T)3 * v3;
+    T e1 = eps2 + c13 * a * a + q * b * b;
+    a = v2 - (T)2 * v3 + v4; b = v2 - v4;
+    T e2 = eps2 + c13 * a * a + q * b * b;
+    a = v3 - (T)2 * v4 + v5; b = (T)3 * v3 - (T)4 * v4 + v5;
+    T e3 = eps2 + c13 * a * a + q * b * b;
+    e1 *= e1; e2 *= e2; e3 *= e3;
+    const T w1 = (T)0.1 * e2 * e3, w2 = (T)0.6 * e1 * e3, w3 = (T)0.3 * e1 * e2;
+    return (w1 * p1 + w2 * p2 + w3 * p3) * fast_rcp(w1 + w2 + w3);
+}
+
+// upwind derivative (times h) at the middle of f0..f6
+template <typename T>
+__device__ __forceinline__ T weno_up(T f0, T f1, T f2, T f3, T f4, T f5, T f6, T vel, T eps2)
+{
+    const T d0 = f1 - f0, d1 = f2 - f1, d2 = f3 - f2, d3 = f4 - f3, d4 = f5 - f4, d5 = f6 - f5;
+    return vel >= (T)0 ? weno5u<T>(d0, d1, d2, d3, d4, eps2) : weno5u<T>(d5, d4, d3, d2, d1, eps2);
+}
+
+template <typename T, bool WALLS>
+__global__ __launch_bounds__(NTH, 2) void k_pred_zm(Batch B, int freeze, int kc)
+{
+    __shared__ Smem<T> S;
+    const int b = blockIdx.y;
+    const Desc& D = *B.d[b];
+    const int nx = D.nx, ny = D.ny, nz = D.nz;
+    const int sxy = nx * ny;
+    const int ps = (int)D.ps;
+    const int ntx = (nx + TX - 1) / TX, nty = (ny + TY - 1) / TY, nch = (nz + kc - 1) / kc;
+    const int nblk = ntx * nty * nch;
+    int bid = blockIdx.x;
+    if ((nblk & 7) == 0) bid = (bid & 7) * (nblk >> 3) + (bid >> 3);     // XCD-contiguous tiles
+    const int tile_x = bid % ntx, tile_y = (bid / ntx) % nty, ch = bid / (ntx * nty);
+    const int i0 = tile_x * TX, j0 = tile_y * TY, k0 = ch * kc;
+    const int k1 = min(k0 + kc, nz);
+    const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+    const int i = i0 + tx, j = j0 + ty;
+    const bool valid = i < nx && j < ny;
+    const int ic = min(i, nx - 1), jc = min(j, ny - 1);
+    const int oij = jc * nx + ic;
+
+    const int st = B.state[b];
+    const T* __restrict__ Bin = (const T*)D.Bt[st & 1];
+    T* __restrict__ Bout = (T*)D.Bt[(st & 1) ^ 1];
+    T* __restrict__ RT = (T*)D.RT;
+    T* __restrict__ RU = (T*)D.RU;
+    const bool euler = (st & ST_EULER) != 0;
+    const T dt = (T)B.dt[b];
+    const T c1 = euler ? (T)1 : (T)1.5, c2 = euler ? (T)0 : (T)-0.5;
+    const bool fene = D.model == EVP_FENE_P, sara = D.model == EVP_SARAMITO;
+    const T G = (T)D.G, L2 = (T)D.L2, afene = (T)D.a_fene, il = (T)D.inv_lam, tyld = (T)D.tau_y;
+    const T idx = (T)D.idx, idy = (T)D.idy, idz = (T)D.idz;
+    const T e2x = (T)(1e-6 * D.dx * D.dx), e2y = (T)(1e-6 * D.dy * D.dy), e2z = (T)(1e-6 * D.dz * D.dz);
+    const double* __restrict__ gu = D.u;
+    const double* __restrict__ gv = D.v;
+    const double* __restrict__ gw = D.w;
+
+    // ---- staging descriptors, computed once: the per-plane offsets do not depend on k ----
+    // B plane with the cross halo: rows j0-1..j0+TY full width, rows j0-3, j0-2, j0+TY+1,
+    // j0+TY+2 only over the tile's columns.
+    constexpr int NB_IN = (TY + 2) * RW, NB_TOT = NB_IN + 4 * TX;
+    constexpr int MB = (NB_TOT + NTH - 1) / NTH, MX = (BOX + NTH - 1) / NTH;
+    // row map of a (possibly ghost) centre row jg: value = wa B[ja] + wb B[jb]
+    auto rowmap = [&](int jg, int& ja, int& jb, T& wa, T& wb) {
+        if (!WALLS) { ja = modp(jg, ny); jb = ja; wa = (T)1; wb = (T)0; return; }
+        if (jg < 0) { const T g = (T)(-jg); ja = 0; jb = 1; wa = (T)1 + g; wb = -g; return; }
+        if (jg >= ny) { const T g = (T)(jg - ny + 1); ja = ny - 1; jb = ny - 2; wa = (T)1 + g; wb = -g; return; }
+        ja = jg; jb = jg; wa = (T)1; wb = (T)0;
+    };
+    int b_l[MB], b_a[MB], b_b[MB];
+    T b_wa[MB], b_wb[MB];
+#pragma unroll
+    for (int m = 0; m < MB; ++m) {
+        const int e = threadIdx.x + m * NTH;
+        int r = 0, c = 3;
+        if (e < NB_IN) { r = 2 + e / RW; c = e % RW; }
+        else if (e < NB_TOT) { const int e2 = e - NB_IN, qq = e2 / TX; r = qq < 2 ? qq : TY + 2 + qq; c = 3 + e2 % TX; }
+        b_l[m] = e < NB_TOT ? r * RW + c : -1;
+        const int ig = modp(i0 + c - 3, nx);
+        int ja, jb;
+        rowmap(j0 + r - 3, ja, jb, b_wa[m], b_wb[m]);
+        b_a[m] = ja * nx + ig;
+        b_b[m] = jb * nx + ig;
+    }
+    // 1-cell box: offsets of B rows (extrapolated ghosts) and of velocity rows (reflected ghosts)
+    int x_l[MX], x_a[MX], x_b[MX], x_v[MX], x_kind[MX];
+    T x_wa[MX], x_wb[MX];
+#pragma unroll
+    for (int m = 0; m < MX; ++m) {
+        const int e = threadIdx.x + m * NTH;
+        const int ee = e < BOX ? e : 0;
+        const int r = ee / BW, c = ee % BW;
+        x_l[m] = e < BOX ? ee : -1;
+        const int ig = modp(i0 + c - 1, nx);
+        const int jg = j0 + r - 1;
+        int ja, jb;
+        rowmap(jg, ja, jb, x_wa[m], x_wb[m]);
+        x_a[m] = ja * nx + ig;
+        x_b[m] = jb * nx + ig;
+        if (!WALLS) { x_v[m] = x_a[m]; x_kind[m] = 0; }
+        else if (jg < 0) { x_v[m] = min(-1 - jg, ny - 1) * nx + ig; x_kind[m] = 1; }
+        else if (jg >= ny) { x_v[m] = max(2 * ny - 1 - jg, 0) * nx + ig; x_kind[m] = 2; }
+        else { x_v[m] = jg * nx + ig; x_kind[m] = (jg == ny - 1) ? 3 : 0; }   // 3: top wall v-face
+    }
+
+    T* const sB = &S.B[0][0][0];
+    // B - I of plane kk with the cross halo into S.B: all loads first, then the LDS stores
+    auto load_bplane = [&](int kk) {
+        const T* bk = Bin + kk * sxy;
+        T v[MB][6];
+#pragma unroll
+        for (int m = 0; m < MB; ++m)
+#pragma unroll
+            for (int cc = 0; cc < 6; ++cc) {
+                T x = bk[cc * ps + b_a[m]];
+                if (WALLS) x = b_wa[m] * x + b_wb[m] * bk[cc * ps + b_b[m]];
+                v[m][cc] = x;
+            }
+#pragma unroll
+        for (int m = 0; m < MB; ++m)
+            if (b_l[m] >= 0)
+#pragma unroll
+                for (int cc = 0; cc < 6; ++cc) sB[cc * (RH * RW) + b_l[m]] = v[m][cc];
+    };
+
+    // box data: stress factors of plane kg (if want_gf), tau_xz/yz/zz and u, v, w of plane kz into
+    // ring slot sl
+    auto load_box = [&](int kg, bool want_gf, int kz, int sl) {
+        const T* bz = Bin + kz * sxy;
+        const T* bg = Bin + kg * sxy;
+        const int kv = kz * sxy;
+        auto bval = [&](const T* p, int cc, int m) {
+            T x = p[cc * ps + x_a[m]];
+            if (WALLS) x = x_wa[m] * x + x_wb[m] * p[cc * ps + x_b[m]];
+            return x;
+        };
+        T z[MX][3], vel[MX][3], gfv[MX], gav[MX];
+#pragma unroll
+        for (int m = 0; m < MX; ++m) {
+            T gfz = G, gaz = (T)0;
+            if (fene) {
+                const T F = L2 / (L2 - (bval(bz, 0, m) + bval(bz, 3, m) + bval(bz, 5, m) + (T)3));
+                gfz = G * F; gaz = G * (F - afene);
+            }
+            z[m][0] = gfz * bval(bz, 2, m);
+            z[m][1] = gfz * bval(bz, 4, m);
+            z[m][2] = gfz * bval(bz, 5, m) + gaz;
+            gfv[m] = G; gav[m] = (T)0;
+            if (want_gf && fene) {
+                const T F = L2 / (L2 - (bval(bg, 0, m) + bval(bg, 3, m) + bval(bg, 5, m) + (T)3));
+                gfv[m] = G * F; gav[m] = G * (F - afene);
+            }
+            const double uu = gu[kv + x_v[m]], vv = gv[kv + x_v[m]], ww = gw[kv + x_v[m]];
+            if (!WALLS || x_kind[m] == 0) { vel[m][0] = (T)uu; vel[m][1] = (T)vv; vel[m][2] = (T)ww; }
+            else if (x_kind[m] == 3) { vel[m][0] = (T)uu; vel[m][1] = (T)0; vel[m][2] = (T)ww; }
+            else {
+                const bool bot = x_kind[m] == 1;
+                vel[m][0] = (T)(2.0 * (bot ? D.u_bot : D.u_top) - uu);
+                vel[m][1] = (T)0;
+                vel[m][2] = (T)(2.0 * (bot ? D.w_bot : D.w_top) - ww);
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < MX; ++m) {
+            const int l = x_l[m];
+            if (l < 0) continue;
+            T* zs = &S.Z[sl][0][0][0];
+            T* vs = &S.V[sl][0][0][0];
+            zs[l] = z[m][0]; zs[BOX + l] = z[m][1]; zs[2 * BOX + l] = z[m][2];
+            vs[l] = vel[m][0]; vs[BOX + l] = vel[m][1]; vs[2 * BOX + l] = vel[m][2];
+            if (want_gf) { (&S.gf[0][0])[l] = gfv[m]; (&S.ga[0][0])[l] = gav[m]; }
+        }
+    };
+
+    // forcing on this thread's x-face row
+    T fx = (T)0;
+    if (D.force_kind == EVP_FORCE_CONST_X) fx = (T)D.force_amp;
+    else if (D.force_kind == EVP_FORCE_SIN_X_OF_Y) fx = (T)(D.force_amp * sin(D.force_ky * (D.y0 + (jc + 0.5) * D.dy)));
+
+    // prologue: register window planes k0-3..k0+2, rings for planes k0-1 and k0
+    T win[7][6];
+#pragma unroll
+    for (int m = 0; m < 6; ++m) {
+        const T* p = Bin + modp(k0 - 3 + m, nz) * sxy + oij;
+#pragma unroll
+        for (int cc = 0; cc < 6; ++cc) win[m][cc] = p[cc * ps];
+    }
+    load_box(0, false, modp(k0 - 1, nz), (k0 + 2) % 3);
+    load_box(0, false, k0, (k0 + 3) % 3);
+
+    const T ms = (T)D.mu_s, irho = (T)D.inv_rho;
+    const T idx2 = idx * idx, idy2 = idy * idy, idz2 = idz * idz;
+    const T h = (T)0.5, qt = (T)0.25;
+    const bool vwall = WALLS && j == ny - 1;
+
+    for (int k = k0; k < k1; ++k) {
+        const int kp = modp(k + 1, nz);
+        {
+            const T* p = Bin + modp(k + 3, nz) * sxy + oij;
+#pragma unroll
+            for (int cc = 0; cc < 6; ++cc) win[6][cc] = p[cc * ps];
+        }
+        load_bplane(k);
+        load_box(k, true, kp, (k + 4) % 3);
+        __syncthreads();
+
+        if (valid) {
+            const int q = k * sxy + j * nx + i;
+            const int r = ty + 3, c = tx + 3, rb = ty + 1, cb = tx + 1;
+            const int sm = (k + 2) % 3, s0 = (k + 3) % 3, sp = (k + 4) % 3;
+#define VU(s, di, dj) S.V[s][0][rb + (dj)][cb + (di)]
+#define VV(s, di, dj) S.V[s][1][rb + (dj)][cb + (di)]
+#define VW(s, di, dj) S.V[s][2][rb + (dj)][cb + (di)]
+            // velocity gradient L_ab = du_a/dx_b at the centre, and the centre velocity
+            T L[3][3];
+            L[0][0] = (VU(s0, 0, 0) - VU(s0, -1, 0)) * idx;
+            L[0][1] = (VU(s0, 0, 1) + VU(s0, -1, 1) - VU(s0, 0, -1) - VU(s0, -1, -1)) * (qt * idy);
+            L[0][2] = (VU(sp, 0, 0) + VU(sp, -1, 0) - VU(sm, 0, 0) - VU(sm, -1, 0)) * (qt * idz);
+            L[1][0] = (VV(s0, 1, 0) + VV(s0, 1, -1) - VV(s0, -1, 0) - VV(s0, -1, -1)) * (qt * idx);
+            L[1][1] = (VV(s0, 0, 0) - VV(s0, 0, -1)) * idy;
+            L[1][2] = (VV(sp, 0, 0) + VV(sp, 0, -1) - VV(sm, 0, 0) - VV(sm, 0, -1)) * (qt * idz);
+            L[2][0] = (VW(s0, 1, 0) + VW(sm, 1, 0) - VW(s0, -1, 0) - VW(sm, -1, 0)) * (qt * idx);
+            L[2][1] = (VW(s0, 0, 1) + VW(sm, 0, 1) - VW(s0, 0, -1) - VW(sm, 0, -1)) * (qt * idy);
+            L[2][2] = (VW(s0, 0, 0) - VW(sm, 0, 0)) * idz;
+            const T uc = h * (VU(s0, 0, 0) + VU(s0, -1, 0));
+            const T vc = h * (VV(s0, 0, 0) + VV(s0, 0, -1));
+            const T wc = h * (VW(s0, 0, 0) + VW(sm, 0, 0));
+
+            // Table 1 closure of this cell
+            const T* bt = win[3];
+            T F = (T)1, a = (T)1;
+            if (fene) {
+                F = L2 / (L2 - (bt[0] + bt[3] + bt[5] + (T)3));
+                a = afene;
+            } else if (sara) {
+                const T t3 = G * (bt[0] + bt[3] + bt[5]) * (T)(1.0 / 3.0);
+                const T dxx = G * bt[0] - t3, dyy = G * bt[3] - t3, dzz = G * bt[5] - t3;
+                const T txy = G * bt[1], txz = G * bt[2], tyz = G * bt[4];
+                const T nrm = sqrt((T)0.5 * (dxx * dxx + dyy * dyy + dzz * dzz)
+                                   + txy * txy + txz * txz + tyz * tyz);
+                F = (tyld == (T)0) ? (T)1 : (nrm > tyld ? (T)1 - tyld / nrm : (T)0);
+                a = F;
+            }
+
+            // stress right-hand side (Eq. rt) and AB2 update (Eq. ab2tau)
+            const int pa[6] = {0, 0, 0, 1, 1, 2}, pb[6] = {0, 1, 2, 1, 2, 2};
+            const int cm[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
+            T rtv[6];
+#pragma unroll
+            for (int cc = 0; cc < 6; ++cc) {
+                const T gx = weno_up<T>(S.B[cc][r][c - 3], S.B[cc][r][c - 2], S.B[cc][r][c - 1], S.B[cc][r][c],
+                                        S.B[cc][r][c + 1], S.B[cc][r][c + 2], S.B[cc][r][c + 3], uc, e2x);
+                const T gy = weno_up<T>(S.B[cc][r - 3][c], S.B[cc][r - 2][c], S.B[cc][r - 1][c], S.B[cc][r][c],
+                                        S.B[cc][r + 1][c], S.B[cc][r + 2][c], S.B[cc][r + 3][c], vc, e2y);
+                const T gz = weno_up<T>(win[0][cc], win[1][cc], win[2][cc], win[3][cc], win[4][cc],
+                                        win[5][cc], win[6][cc], wc, e2z);
+                const T adv = uc * gx * idx + vc * gy * idy + wc * gz * idz;
+                const int p = pa[cc], rr = pb[cc];
+                T ucv = L[p][rr] + L[rr][p];
+#pragma unroll
+                for (int m = 0; m < 3; ++m) ucv += L[p][m] * bt[cm[m][rr]] + bt[cm[p][m]] * L[rr][m];
+                const T relax = (((p == rr) ? (a - F) : (T)0) - F * bt[cc]) * il;
+                rtv[cc] = relax - adv + ucv;
+            }
+#pragma unroll
+            for (int cc = 0; cc < 6; ++cc) {
+                const T old = euler ? (T)0 : RT[cc * ps + q];
+                Bout[cc * ps + q] = bt[cc] + dt * (c1 * rtv[cc] + c2 * old);
+                RT[cc * ps + q] = rtv[cc];
+            }
+
+            if (freeze) {
+                D.us[q] = gu[q]; D.vs[q] = gv[q]; D.ws[q] = gw[q];
+                RU[q] = (T)0; RU[ps + q] = (T)0; RU[2 * ps + q] = (T)0;
+            } else {
+                // stresses of plane k from B - I and the staged factors
+#define TK(cc, di, dj) (fene ? (S.gf[rb + (dj)][cb + (di)] * S.B[cc][r + (dj)][c + (di)] + \
+                        (((cc) == 0 || (cc) == 3 || (cc) == 5) ? S.ga[rb + (dj)][cb + (di)] : (T)0)) \
+                        : G * S.B[cc][r + (dj)][c + (di)])
+#define TZ(s, zc, di, dj) S.Z[s][zc][rb + (dj)][cb + (di)]
+                // x-face (i+1/2, j, k)
+                T rux;
+                {
+                    const T u0 = VU(s0, 0, 0), ue = VU(s0, 1, 0), uw = VU(s0, -1, 0);
+                    const T un = VU(s0, 0, 1), us = VU(s0, 0, -1), uf = VU(sp, 0, 0), ub = VU(sm, 0, 0);
+                    const T cR = h * (u0 + ue), cL = h * (uw + u0);
+                    const T vT = h * (VV(s0, 0, 0) + VV(s0, 1, 0)), vB = h * (VV(s0, 0, -1) + VV(s0, 1, -1));
+                    const T wF = h * (VW(s0, 0, 0) + VW(s0, 1, 0)), wB = h * (VW(sm, 0, 0) + VW(sm, 1, 0));
+                    const T adv = (cR * cR - cL * cL) * idx + (vT * h * (u0 + un) - vB * h * (us + u0)) * idy
+                                + (wF * h * (u0 + uf) - wB * h * (ub + u0)) * idz;
+                    const T lap = (ue - (T)2 * u0 + uw) * idx2 + (un - (T)2 * u0 + us) * idy2
+                                + (uf - (T)2 * u0 + ub) * idz2;
+                    const T dtau = (TK(0, 1, 0) - TK(0, 0, 0)) * idx
+                                 + qt * (TK(1, 0, 1) + TK(1, 1, 1) - TK(1, 0, -1) - TK(1, 1, -1)) * idy
+                                 + qt * (TZ(sp, 0, 0, 0) + TZ(sp, 0, 1, 0) - TZ(sm, 0, 0, 0) - TZ(sm, 0, 1, 0)) * idz;
+                    rux = -adv + (ms * lap + dtau + fx) * irho;
+                }
+                // y-face (i, j+1/2, k)
+                T ruy = (T)0;
+                if (!vwall) {
+                    const T v0 = VV(s0, 0, 0), vn = VV(s0, 0, 1), vs = VV(s0, 0, -1);
+                    const T ve = VV(s0, 1, 0), vw = VV(s0, -1, 0), vf = VV(sp, 0, 0), vb = VV(sm, 0, 0);
+                    const T cT = h * (v0 + vn), cB = h * (vs + v0);
+                    const T uR = h * (VU(s0, 0, 0) + VU(s0, 0, 1)), uL = h * (VU(s0, -1, 0) + VU(s0, -1, 1));
+                    const T wF = h * (VW(s0, 0, 0) + VW(s0, 0, 1)), wB = h * (VW(sm, 0, 0) + VW(sm, 0, 1));
+                    const T adv = (uR * h * (v0 + ve) - uL * h * (vw + v0)) * idx + (cT * cT - cB * cB) * idy
+                                + (wF * h * (v0 + vf) - wB * h * (vb + v0)) * idz;
+                    const T lap = (ve - (T)2 * v0 + vw) * idx2 + (vn - (T)2 * v0 + vs) * idy2
+                                + (vf - (T)2 * v0 + vb) * idz2;
+                    const T dtau = qt * (TK(1, 1, 0) + TK(1, 1, 1) - TK(1, -1, 0) - TK(1, -1, 1)) * idx
+                                 + (TK(3, 0, 1) - TK(3, 0, 0)) * idy
+                                 + qt * (TZ(sp, 1, 0, 0) + TZ(sp, 1, 0, 1) - TZ(sm, 1, 0, 0) - TZ(sm, 1, 0, 1)) * idz;
+                    ruy = -adv + (ms * lap + dtau) * irho;
+                }
+                // z-face (i, j, k+1/2)
+                T ruz;
+                {
+                    const T w0 = VW(s0, 0, 0), wf = VW(sp, 0, 0), wb = VW(sm, 0, 0);
+                    const T we = VW(s0, 1, 0), ww = VW(s0, -1, 0), wn = VW(s0, 0, 1), wsv = VW(s0, 0, -1);
+                    const T cF = h * (w0 + wf), cB = h * (wb + w0);
+                    const T uR = h * (VU(s0, 0, 0) + VU(sp, 0, 0)), uL = h * (VU(s0, -1, 0) + VU(sp, -1, 0));
+                    const T vT = h * (VV(s0, 0, 0) + VV(sp, 0, 0)), vB = h * (VV(s0, 0, -1) + VV(sp, 0, -1));
+                    const T adv = (uR * h * (w0 + we) - uL * h * (ww + w0)) * idx
+                                + (vT * h * (w0 + wn) - vB * h * (wsv + w0)) * idy + (cF * cF - cB * cB) * idz;
+                    const T lap = (we - (T)2 * w0 + ww) * idx2 + (wn - (T)2 * w0 + wsv) * idy2
+                                + (wf - (T)2 * w0 + wb) * idz2;
+                    const T dtau = qt * (TZ(s0, 0, 1, 0) + TZ(sp, 0, 1, 0) - TZ(s0, 0, -1, 0) - TZ(sp, 0, -1, 0)) * idx
+                                 + qt * (TZ(s0, 1, 0, 1) + TZ(sp, 1, 0, 1) - TZ(s0, 1, 0, -1) - TZ(sp, 1, 0, -1)) * idy
+                                 + (TZ(sp, 2, 0, 0) - TZ(s0, 2, 0, 0)) * idz;
+                    ruz = -adv + (ms * lap + dtau) * irho;
+                }
+#undef TK
+#undef TZ
+                const T ox = euler ? (T)0 : RU[q], oy = euler ? (T)0 : RU[ps + q], oz = euler ? (T)0 : RU[2 * ps + q];
+                D.us[q] = gu[q] + (double)(dt * (c1 * rux + c2 * ox));
+                D.vs[q] = vwall ? 0.0 : gv[q] + (double)(dt * (c1 * ruy + c2 * oy));
+                D.ws[q] = gw[q] + (double)(dt * (c1 * ruz + c2 * oz));
+                RU[q] = rux; RU[ps + q] = ruy; RU[2 * ps + q] = ruz;
+            }
+#undef VU
+#undef VV
+#undef VW
+        }
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < 6; ++m)
+#pragma unroll
+            for (int cc = 0; cc < 6; ++cc) win[m][cc] = win[m + 1][cc];
+    }
+}
+
+}  // namespace
+
+// planes per block: about two resident blocks per CU on 256 CUs, at least 4 planes per block
+int predictor_chunk(int nx, int ny, int nz)
+{
+    static const int target = [] {
+        const char* e = std::getenv("EVP_PRED_BLOCKS");
+        const int v = e ? std::atoi(e) : 0;
+        return v > 0 ? v : 512;
+    }();
+    const int tiles = ((nx + TX - 1) / TX) * ((ny + TY - 1) / TY);
+    int nch = (target + tiles - 1) / tiles;
+    nch = max(1, min(nch, nz / 4));
+    return (nz + nch - 1) / nch;
+}
+
+hipError_t launch_predictor_zm(const Batch& b, int precision, int nx, int ny, int nz, bool freeze,
+                               hipStream_t s, bool walls)
+{
+    const int kc = predictor_chunk(nx, ny, nz);
+    const int nblk = ((nx + TX - 1) / TX) * ((ny + TY - 1) / TY) * ((nz + kc - 1) / kc);
+    dim3 grid(nblk, b.count);
+    const int fz = freeze ? 1 : 0;
+    if (precision == EVP_MIXED) {
+        if (walls) hipLaunchKernelGGL((k_pred_zm<float, true>), grid, dim3(NTH), 0, s, b, fz, kc);
+        else hipLaunchKernelGGL((k_pred_zm<float, false>), grid, dim3(NTH), 0, s, b, fz, kc);
+    } else {
+        if (walls) hipLaunchKernelGGL((k_pred_zm<double, true>), grid, dim3(NTH), 0, s, b, fz, kc);
+        else hipLaunchKernelGGL((k_pred_zm<double, false>), grid, dim3(NTH), 0, s, b, fz, kc);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace evp

@@ -44,7 +44,9 @@ def oracle_state(s):
 
 def field_errors(ref: dict, got: dict):
     """Max errors: velocity components relative to the largest velocity magnitude, B - I
-    components relative to the largest |B - I|, p relative to max |p - mean p|."""
+    components relative to the largest |B - I|, p relative to max |p - mean p| (floored at
+    1e-6 rho U^2, so a flow whose pressure is identically zero compares rounding noise against
+    a physical pressure scale)."""
     err = {}
     vmax = max(np.abs(ref[k]).max() for k in ("u", "v", "w"))
     for k in ("u", "v", "w"):
@@ -59,7 +61,7 @@ def field_errors(ref: dict, got: dict):
     if "p" in ref and "p" in got:
         rp = ref["p"] - ref["p"].mean()
         gp = got["p"] - got["p"].mean()
-        err["p"] = float(np.abs(gp - rp).max() / max(np.abs(rp).max(), 1e-300))
+        err["p"] = float(np.abs(gp - rp).max() / max(np.abs(rp).max(), 1e-6 * vmax ** 2, 1e-300))
     return err
 
 
