@@ -78,7 +78,11 @@ template <typename T>
 __device__ __forceinline__ T weno_up(T f0, T f1, T f2, T f3, T f4, T f5, T f6, T vel, T eps2)
 {
     const T d0 = f1 - f0, d1 = f2 - f1, d2 = f3 - f2, d3 = f4 - f3, d4 = f5 - f4, d5 = f6 - f5;
-    return vel >= (T)0 ? weno5u<T>(d0, d1, d2, d3, d4, eps2) : weno5u<T>(d5, d4, d3, d2, d1, eps2);
+    // pick the upwind-side differences with selects, then evaluate one WENO (no divergence)
+    const bool pos = vel >= (T)0;
+    const T v1 = pos ? d0 : d5, v2 = pos ? d1 : d4, v3 = pos ? d2 : d3;
+    const T v4 = pos ? d3 : d2, v5 = pos ? d4 : d1;
+    return weno5u<T>(v1, v2, v3, v4, v5, eps2);
 }
 
 template <typename T, bool WALLS>
@@ -325,6 +329,8 @@ __global__ __launch_bounds__(NTH, 2) void k_pred_zm(Batch B, int freeze, int kc)
                 for (int m = 0; m < 3; ++m) ucv += L[p][m] * bt[cm[m][rr]] + bt[cm[p][m]] * L[rr][m];
                 const T relax = (((p == rr) ? (a - F) : (T)0) - F * bt[cc]) * il;
                 rtv[cc] = relax - adv + ucv;
+                // bound live ranges: finish this component before the next one's LDS reads
+                __asm__ volatile("" ::"v"(rtv[cc]) : "memory");
             }
 #pragma unroll
             for (int cc = 0; cc < 6; ++cc) {
@@ -333,6 +339,7 @@ __global__ __launch_bounds__(NTH, 2) void k_pred_zm(Batch B, int freeze, int kc)
                 RT[cc * ps + q] = rtv[cc];
             }
 
+            __asm__ volatile("" ::: "memory");
             if (freeze) {
                 D.us[q] = gu[q]; D.vs[q] = gv[q]; D.ws[q] = gw[q];
                 RU[q] = (T)0; RU[ps + q] = (T)0; RU[2 * ps + q] = (T)0;
