@@ -124,10 +124,15 @@ __global__ __launch_bounds__(NTH, 2) void k_pred_zm(Batch B, int freeze, int kc)
     const double* __restrict__ gw = D.w;
 
     // ---- staging descriptors, computed once: the per-plane offsets do not depend on k ----
-    // B plane with the cross halo: rows j0-1..j0+TY full width, rows j0-3, j0-2, j0+TY+1,
-    // j0+TY+2 only over the tile's columns.
-    constexpr int NB_IN = (TY + 2) * RW, NB_TOT = NB_IN + 4 * TX;
-    constexpr int MB = (NB_TOT + NTH - 1) / NTH, MX = (BOX + NTH - 1) / NTH;
+    // Interior slots (the block's own cells) are filled from the thread's register window; only
+    // halo slots, and interior slots of threads whose cell lies outside the domain (ragged
+    // tiles: periodic image or wall ghost), are read from global memory.
+    // B-plane halo: rows j0-1 and j0+TY over the full width, columns i0-3..i0-1 and
+    // i0+TX..i0+TX+2 of the tile's rows, and the arm rows j0-3, j0-2, j0+TY+1, j0+TY+2 over the
+    // tile's columns.  Box halo: the 1-cell ring.
+    constexpr int NHB = 2 * RW + 6 * TY + 4 * TX;
+    constexpr int NHX = 2 * BW + 2 * TY;
+    static_assert(NHB <= NTH && NHX <= NTH, "one halo slot per thread");
     // row map of a (possibly ghost) centre row jg: value = wa B[ja] + wb B[jb]
     auto rowmap = [&](int jg, int& ja, int& jb, T& wa, T& wb) {
         if (!WALLS) { ja = modp(jg, ny); jb = ja; wa = (T)1; wb = (T)0; return; }
@@ -135,109 +140,129 @@ __global__ __launch_bounds__(NTH, 2) void k_pred_zm(Batch B, int freeze, int kc)
         if (jg >= ny) { const T g = (T)(jg - ny + 1); ja = ny - 1; jb = ny - 2; wa = (T)1 + g; wb = -g; return; }
         ja = jg; jb = jg; wa = (T)1; wb = (T)0;
     };
-    int b_l[MB], b_a[MB], b_b[MB];
-    T b_wa[MB], b_wb[MB];
-#pragma unroll
-    for (int m = 0; m < MB; ++m) {
-        const int e = threadIdx.x + m * NTH;
-        int r = 0, c = 3;
-        if (e < NB_IN) { r = 2 + e / RW; c = e % RW; }
-        else if (e < NB_TOT) { const int e2 = e - NB_IN, qq = e2 / TX; r = qq < 2 ? qq : TY + 2 + qq; c = 3 + e2 % TX; }
-        b_l[m] = e < NB_TOT ? r * RW + c : -1;
-        const int ig = modp(i0 + c - 3, nx);
-        int ja, jb;
-        rowmap(j0 + r - 3, ja, jb, b_wa[m], b_wb[m]);
-        b_a[m] = ja * nx + ig;
-        b_b[m] = jb * nx + ig;
+    struct Src { int a, b; T wa, wb; };          // B value = wa B[a] + wb B[b] (plane-relative)
+    struct VSrc { int o, kind; };                  // velocity row offset; 0 inner, 1/2 ghost, 3 top v-face
+    auto bsrc = [&](int ig, int jg) {
+        Src q; int ja, jb; rowmap(jg, ja, jb, q.wa, q.wb);
+        q.a = ja * nx + ig; q.b = jb * nx + ig; return q;
+    };
+    auto vsrc = [&](int ig, int jg) {
+        VSrc q;
+        if (!WALLS) { q.o = modp(jg, ny) * nx + ig; q.kind = 0; }
+        else if (jg < 0) { q.o = min(-1 - jg, ny - 1) * nx + ig; q.kind = 1; }
+        else if (jg >= ny) { q.o = max(2 * ny - 1 - jg, 0) * nx + ig; q.kind = 2; }
+        else { q.o = jg * nx + ig; q.kind = (jg == ny - 1) ? 3 : 0; }
+        return q;
+    };
+    const int t = threadIdx.x;
+    int hb_l = -1;
+    Src hb{0, 0, (T)1, (T)0};
+    if (t < NHB) {
+        int r, c;
+        if (t < 2 * RW) { r = t < RW ? 2 : TY + 3; c = t % RW; }
+        else if (t < 2 * RW + 6 * TY) { const int u = t - 2 * RW, c6 = u % 6; r = 3 + u / 6; c = c6 < 3 ? c6 : TX + c6; }
+        else { const int u = t - 2 * RW - 6 * TY, qq = u / TX; r = qq < 2 ? qq : TY + 2 + qq; c = 3 + u % TX; }
+        hb_l = r * RW + c;
+        hb = bsrc(modp(i0 + c - 3, nx), j0 + r - 3);
     }
-    // 1-cell box: offsets of B rows (extrapolated ghosts) and of velocity rows (reflected ghosts)
-    int x_l[MX], x_a[MX], x_b[MX], x_v[MX], x_kind[MX];
-    T x_wa[MX], x_wb[MX];
-#pragma unroll
-    for (int m = 0; m < MX; ++m) {
-        const int e = threadIdx.x + m * NTH;
-        const int ee = e < BOX ? e : 0;
-        const int r = ee / BW, c = ee % BW;
-        x_l[m] = e < BOX ? ee : -1;
-        const int ig = modp(i0 + c - 1, nx);
-        const int jg = j0 + r - 1;
-        int ja, jb;
-        rowmap(jg, ja, jb, x_wa[m], x_wb[m]);
-        x_a[m] = ja * nx + ig;
-        x_b[m] = jb * nx + ig;
-        if (!WALLS) { x_v[m] = x_a[m]; x_kind[m] = 0; }
-        else if (jg < 0) { x_v[m] = min(-1 - jg, ny - 1) * nx + ig; x_kind[m] = 1; }
-        else if (jg >= ny) { x_v[m] = max(2 * ny - 1 - jg, 0) * nx + ig; x_kind[m] = 2; }
-        else { x_v[m] = jg * nx + ig; x_kind[m] = (jg == ny - 1) ? 3 : 0; }   // 3: top wall v-face
+    int hx_l = -1;
+    Src hx{0, 0, (T)1, (T)0};
+    VSrc hv{0, 0};
+    if (t < NHX) {
+        int r, c;
+        if (t < 2 * BW) { r = t < BW ? 0 : TY + 1; c = t % BW; }
+        else { const int u = t - 2 * BW; r = 1 + u / 2; c = (u & 1) ? TX + 1 : 0; }
+        hx_l = r * BW + c;
+        hx = bsrc(modp(i0 + c - 1, nx), j0 + r - 1);
+        hv = vsrc(modp(i0 + c - 1, nx), j0 + r - 1);
     }
+    const int own_b = (ty + 3) * RW + (tx + 3), own_x = (ty + 1) * BW + (tx + 1);
+    const Src os = bsrc(modp(i, nx), j);           // used only when the cell is outside the domain
+    const VSrc ov = vsrc(modp(i, nx), j);
 
-    T* const sB = &S.B[0][0][0];
-    // B - I of plane kk with the cross halo into S.B: all loads first, then the LDS stores
-    auto load_bplane = [&](int kk) {
-        const T* bk = Bin + kk * sxy;
-        T v[MB][6];
-#pragma unroll
-        for (int m = 0; m < MB; ++m)
-#pragma unroll
-            for (int cc = 0; cc < 6; ++cc) {
-                T x = bk[cc * ps + b_a[m]];
-                if (WALLS) x = b_wa[m] * x + b_wb[m] * bk[cc * ps + b_b[m]];
-                v[m][cc] = x;
-            }
-#pragma unroll
-        for (int m = 0; m < MB; ++m)
-            if (b_l[m] >= 0)
-#pragma unroll
-                for (int cc = 0; cc < 6; ++cc) sB[cc * (RH * RW) + b_l[m]] = v[m][cc];
+    auto bload = [&](const T* p, int cc, const Src& q) {
+        T x = p[cc * ps + q.a];
+        if (WALLS) x = q.wa * x + q.wb * p[cc * ps + q.b];
+        return x;
+    };
+    auto vload = [&](int kv, const VSrc& q, T* out) {
+        const double uu = gu[kv + q.o], vv = gv[kv + q.o], ww = gw[kv + q.o];
+        if (!WALLS || q.kind == 0) { out[0] = (T)uu; out[1] = (T)vv; out[2] = (T)ww; }
+        else if (q.kind == 3) { out[0] = (T)uu; out[1] = (T)0; out[2] = (T)ww; }
+        else {
+            const bool bot = q.kind == 1;
+            out[0] = (T)(2.0 * (bot ? D.u_bot : D.u_top) - uu);
+            out[1] = (T)0;
+            out[2] = (T)(2.0 * (bot ? D.w_bot : D.w_top) - ww);
+        }
+    };
+    // stress factors G F, G (F - a) of a B - I value set
+    auto factors = [&](T b0, T b3, T b5, T& gfo, T& gao) {
+        gfo = G; gao = (T)0;
+        if (fene) {
+            const T F = L2 / (L2 - (b0 + b3 + b5 + (T)3));
+            gfo = G * F; gao = G * (F - afene);
+        }
     };
 
-    // box data: stress factors of plane kg (if want_gf), tau_xz/yz/zz and u, v, w of plane kz into
-    // ring slot sl
-    auto load_box = [&](int kg, bool want_gf, int kz, int sl) {
+    T* const sB = &S.B[0][0][0];
+    // B - I of plane kk with the cross halo into S.B (own value: the window entry of plane kk)
+    auto load_bplane = [&](int kk, const T* own) {
+        const T* bk = Bin + kk * sxy;
+        T hvv[6], ovv[6];
+#pragma unroll
+        for (int cc = 0; cc < 6; ++cc) {
+            hvv[cc] = (hb_l >= 0) ? bload(bk, cc, hb) : (T)0;
+            ovv[cc] = valid ? own[cc] : bload(bk, cc, os);
+        }
+#pragma unroll
+        for (int cc = 0; cc < 6; ++cc) {
+            if (hb_l >= 0) sB[cc * (RH * RW) + hb_l] = hvv[cc];
+            sB[cc * (RH * RW) + own_b] = ovv[cc];
+        }
+    };
+
+    // ring slot sl <- tau_xz, tau_yz, tau_zz and u, v, w of plane kz (own B - I values: ownz);
+    // if ownk != nullptr also the stress factors of plane k (own values: ownk)
+    auto load_box = [&](int kz, const T* ownz, int sl, int kg, const T* ownk) {
         const T* bz = Bin + kz * sxy;
         const T* bg = Bin + kg * sxy;
         const int kv = kz * sxy;
-        auto bval = [&](const T* p, int cc, int m) {
-            T x = p[cc * ps + x_a[m]];
-            if (WALLS) x = x_wa[m] * x + x_wb[m] * p[cc * ps + x_b[m]];
-            return x;
-        };
-        T z[MX][3], vel[MX][3], gfv[MX], gav[MX];
+        // halo slot
+        T hz[3], hvel[3], hgf = G, hga = (T)0;
+        if (hx_l >= 0) {
+            T gf, ga;
+            if (fene) factors(bload(bz, 0, hx), bload(bz, 3, hx), bload(bz, 5, hx), gf, ga);
+            else { gf = G; ga = (T)0; }
+            hz[0] = gf * bload(bz, 2, hx); hz[1] = gf * bload(bz, 4, hx); hz[2] = gf * bload(bz, 5, hx) + ga;
+            vload(kv, hv, hvel);
+            if (ownk && fene) factors(bload(bg, 0, hx), bload(bg, 3, hx), bload(bg, 5, hx), hgf, hga);
+        }
+        // own slot
+        T oz[3], ovel[3], ogf = G, oga = (T)0;
+        {
+            T zb[6];
 #pragma unroll
-        for (int m = 0; m < MX; ++m) {
-            T gfz = G, gaz = (T)0;
-            if (fene) {
-                const T F = L2 / (L2 - (bval(bz, 0, m) + bval(bz, 3, m) + bval(bz, 5, m) + (T)3));
-                gfz = G * F; gaz = G * (F - afene);
-            }
-            z[m][0] = gfz * bval(bz, 2, m);
-            z[m][1] = gfz * bval(bz, 4, m);
-            z[m][2] = gfz * bval(bz, 5, m) + gaz;
-            gfv[m] = G; gav[m] = (T)0;
-            if (want_gf && fene) {
-                const T F = L2 / (L2 - (bval(bg, 0, m) + bval(bg, 3, m) + bval(bg, 5, m) + (T)3));
-                gfv[m] = G * F; gav[m] = G * (F - afene);
-            }
-            const double uu = gu[kv + x_v[m]], vv = gv[kv + x_v[m]], ww = gw[kv + x_v[m]];
-            if (!WALLS || x_kind[m] == 0) { vel[m][0] = (T)uu; vel[m][1] = (T)vv; vel[m][2] = (T)ww; }
-            else if (x_kind[m] == 3) { vel[m][0] = (T)uu; vel[m][1] = (T)0; vel[m][2] = (T)ww; }
-            else {
-                const bool bot = x_kind[m] == 1;
-                vel[m][0] = (T)(2.0 * (bot ? D.u_bot : D.u_top) - uu);
-                vel[m][1] = (T)0;
-                vel[m][2] = (T)(2.0 * (bot ? D.w_bot : D.w_top) - ww);
+            for (int cc = 0; cc < 6; ++cc) zb[cc] = (cc == 1) ? (T)0 : (valid ? ownz[cc] : bload(bz, cc, os));
+            T gf, ga;
+            factors(zb[0], zb[3], zb[5], gf, ga);
+            oz[0] = gf * zb[2]; oz[1] = gf * zb[4]; oz[2] = gf * zb[5] + ga;
+            vload(kv, ov, ovel);
+            if (ownk && fene) {
+                if (valid) factors(ownk[0], ownk[3], ownk[5], ogf, oga);
+                else factors(bload(bg, 0, os), bload(bg, 3, os), bload(bg, 5, os), ogf, oga);
             }
         }
-#pragma unroll
-        for (int m = 0; m < MX; ++m) {
-            const int l = x_l[m];
-            if (l < 0) continue;
-            T* zs = &S.Z[sl][0][0][0];
-            T* vs = &S.V[sl][0][0][0];
-            zs[l] = z[m][0]; zs[BOX + l] = z[m][1]; zs[2 * BOX + l] = z[m][2];
-            vs[l] = vel[m][0]; vs[BOX + l] = vel[m][1]; vs[2 * BOX + l] = vel[m][2];
-            if (want_gf) { (&S.gf[0][0])[l] = gfv[m]; (&S.ga[0][0])[l] = gav[m]; }
+        T* zs = &S.Z[sl][0][0][0];
+        T* vs = &S.V[sl][0][0][0];
+        if (hx_l >= 0) {
+            zs[hx_l] = hz[0]; zs[BOX + hx_l] = hz[1]; zs[2 * BOX + hx_l] = hz[2];
+            vs[hx_l] = hvel[0]; vs[BOX + hx_l] = hvel[1]; vs[2 * BOX + hx_l] = hvel[2];
+            if (ownk) { (&S.gf[0][0])[hx_l] = hgf; (&S.ga[0][0])[hx_l] = hga; }
         }
+        zs[own_x] = oz[0]; zs[BOX + own_x] = oz[1]; zs[2 * BOX + own_x] = oz[2];
+        vs[own_x] = ovel[0]; vs[BOX + own_x] = ovel[1]; vs[2 * BOX + own_x] = ovel[2];
+        if (ownk) { (&S.gf[0][0])[own_x] = ogf; (&S.ga[0][0])[own_x] = oga; }
     };
 
     // forcing on this thread's x-face row
@@ -253,8 +278,8 @@ __global__ __launch_bounds__(NTH, 2) void k_pred_zm(Batch B, int freeze, int kc)
 #pragma unroll
         for (int cc = 0; cc < 6; ++cc) win[m][cc] = p[cc * ps];
     }
-    load_box(0, false, modp(k0 - 1, nz), (k0 + 2) % 3);
-    load_box(0, false, k0, (k0 + 3) % 3);
+    load_box(modp(k0 - 1, nz), win[2], (k0 + 2) % 3, 0, nullptr);
+    load_box(k0, win[3], (k0 + 3) % 3, 0, nullptr);
 
     const T ms = (T)D.mu_s, irho = (T)D.inv_rho;
     const T idx2 = idx * idx, idy2 = idy * idy, idz2 = idz * idz;
@@ -268,8 +293,8 @@ __global__ __launch_bounds__(NTH, 2) void k_pred_zm(Batch B, int freeze, int kc)
 #pragma unroll
             for (int cc = 0; cc < 6; ++cc) win[6][cc] = p[cc * ps];
         }
-        load_bplane(k);
-        load_box(k, true, kp, (k + 4) % 3);
+        load_bplane(k, win[3]);
+        load_box(kp, win[4], (k + 4) % 3, k, win[3]);
         __syncthreads();
 
         if (valid) {
