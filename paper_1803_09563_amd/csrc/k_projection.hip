@@ -172,31 +172,69 @@ __global__ __launch_bounds__(NT) void k_solve_periodic(Batch B)
 // ---------------------------------------------------------------------------------------------
 // walls: tridiagonal solve in y for every (kx, kz), pivots precomputed per (kx, |kz|)
 // ---------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_thomas(Batch B)
+constexpr int TH_NT = 64;   // one wave per block: modes are few, spread them over all CUs
+constexpr int TH_P = 8;     // rows loaded ahead of the dependent recurrence
+
+__global__ __launch_bounds__(TH_NT) void k_thomas(Batch B)
 {
     const Desc& D = *B.d[blockIdx.y];
     const int nh = D.nh, ny = D.ny, nz = D.nz;
-    const int col = blockIdx.x * 256 + threadIdx.x;
+    const int col = blockIdx.x * TH_NT + threadIdx.x;
     if (col >= nh * nz) return;
     const int kz = col / nh, kx = col - kz * nh;
     const int kzs = kz <= nz - kz ? kz : nz - kz;
-    const double* piv = D.piv + (long long)kzs * ny * nh + kx;
-    double2* s = D.spec + (long long)kz * ny * nh + kx;
+    const double* __restrict__ piv = D.piv + (long long)kzs * ny * nh + kx;
+    double2* __restrict__ s = D.spec + (long long)kz * ny * nh + kx;
     const double a = D.idy * D.idy;                  // sub- and super-diagonal 1/dy^2
     const double scale = 1.0 / ((double)D.nx * nz);  // inverse x and z transforms
+    // forward sweep d'_j = (r_j - a d'_{j-1}) / (b_j - a c'_{j-1}); the loads of the next block
+    // of TH_P rows are issued before the dependent updates of the current one
     double2 dp = make_double2(0.0, 0.0);
-    for (int j = 0; j < ny; ++j) {
-        const double2 r = s[(long long)j * nh];
-        const double iv = piv[(long long)j * nh];
-        dp = make_double2((scale * r.x - a * dp.x) * iv, (scale * r.y - a * dp.y) * iv);
-        s[(long long)j * nh] = dp;
+    double2 r[TH_P], rn[TH_P];
+    double iv[TH_P], ivn[TH_P];
+    auto fload = [&](int j0, double2* rr, double* ii) {
+#pragma unroll
+        for (int m = 0; m < TH_P; ++m) {
+            const int jj = min(j0 + m, ny - 1);
+            rr[m] = s[(long long)jj * nh];
+            ii[m] = piv[(long long)jj * nh];
+        }
+    };
+    fload(0, r, iv);
+    for (int j0 = 0; j0 < ny; j0 += TH_P) {
+        if (j0 + TH_P < ny) fload(j0 + TH_P, rn, ivn);
+#pragma unroll
+        for (int m = 0; m < TH_P; ++m) {
+            if (j0 + m < ny) {
+                dp = make_double2((scale * r[m].x - a * dp.x) * iv[m], (scale * r[m].y - a * dp.y) * iv[m]);
+                s[(long long)(j0 + m) * nh] = dp;
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < TH_P; ++m) { r[m] = rn[m]; iv[m] = ivn[m]; }
     }
+    // backward sweep x_j = d'_j - c'_j x_{j+1}, c'_j = a / (b_j - a c'_{j-1})
     double2 x = dp;
-    for (int j = ny - 2; j >= 0; --j) {
-        const double2 d = s[(long long)j * nh];
-        const double cp = a * piv[(long long)j * nh];
-        x = make_double2(d.x - cp * x.x, d.y - cp * x.y);
-        s[(long long)j * nh] = x;
+    auto bload = [&](int j1, double2* dd, double* cc) {
+#pragma unroll
+        for (int m = 0; m < TH_P; ++m) {
+            const int jj = max(j1 - m, 0);
+            dd[m] = s[(long long)jj * nh];
+            cc[m] = a * piv[(long long)jj * nh];
+        }
+    };
+    if (ny >= 2) bload(ny - 2, r, iv);
+    for (int j1 = ny - 2; j1 >= 0; j1 -= TH_P) {
+        if (j1 - TH_P >= 0) bload(j1 - TH_P, rn, ivn);
+#pragma unroll
+        for (int m = 0; m < TH_P; ++m) {
+            if (j1 - m >= 0) {
+                x = make_double2(r[m].x - iv[m] * x.x, r[m].y - iv[m] * x.y);
+                s[(long long)(j1 - m) * nh] = x;
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < TH_P; ++m) { r[m] = rn[m]; iv[m] = ivn[m]; }
     }
     if (kx == 0 && kz == 0) {
         // gauge: zero volume mean of p is zero mean of the (0,0) mode over y
@@ -383,8 +421,8 @@ hipError_t launch_solve_periodic(const Batch& b, int nx, int ny, int nz, hipStre
 hipError_t launch_thomas(const Batch& b, int nx, int ny, int nz, hipStream_t s)
 {
     const int cols = (nx / 2 + 1) * nz;
-    dim3 grid((cols + 255) / 256, b.count);
-    hipLaunchKernelGGL(k_thomas, grid, dim3(256), 0, s, b);
+    dim3 grid((cols + TH_NT - 1) / TH_NT, b.count);
+    hipLaunchKernelGGL(k_thomas, grid, dim3(TH_NT), 0, s, b);
     return hipGetLastError();
 }
 
