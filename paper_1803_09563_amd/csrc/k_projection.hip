@@ -20,6 +20,48 @@ constexpr int TK = 16;     // consecutive kx per block in the strided passes
 
 __device__ __forceinline__ int wrapi(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
+// Strided tile <-> LDS: element e = tid + m NT of the N x TK tile is (row n = e / TK, column
+// c = e % TK).  The column is the same for every m of a thread, so its bounds check is hoisted;
+// loads are issued in groups of up to 16 before their LDS stores.
+template <int N, bool CONJ>
+__device__ __forceinline__ void tile_in(double2* buf, const double2* __restrict__ src, long long es,
+                                        bool colok, int tid)
+{
+    constexpr int TOT = N * TK, M = (TOT + NT - 1) / NT, G = M < 16 ? M : 16;
+    const int c = tid % TK, n0 = tid / TK;
+#pragma unroll
+    for (int g0 = 0; g0 < M; g0 += G) {
+        double2 v[G];
+#pragma unroll
+        for (int m = 0; m < G; ++m) {
+            const int n = n0 + (g0 + m) * (NT / TK);
+            v[m] = (colok && n < N) ? src[n * es + c] : make_double2(0.0, 0.0);
+        }
+#pragma unroll
+        for (int m = 0; m < G; ++m) {
+            const int n = n0 + (g0 + m) * (NT / TK);
+            if (n < N) buf[n * TK + c] = CONJ ? cconj(v[m]) : v[m];
+        }
+    }
+}
+
+template <int N, bool CONJ>
+__device__ __forceinline__ void tile_out(const double2* buf, double2* __restrict__ dst, long long es,
+                                         bool colok, int tid)
+{
+    constexpr int TOT = N * TK, M = (TOT + NT - 1) / NT;
+    const int c = tid % TK, n0 = tid / TK;
+    if (!colok) return;
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        const int n = n0 + m * (NT / TK);
+        if (n < N) {
+            const double2 x = buf[n * TK + c];
+            dst[n * es + c] = CONJ ? cconj(x) : x;
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------------------------
 // div + forward x transform
 // ---------------------------------------------------------------------------------------------
@@ -41,29 +83,51 @@ __global__ __launch_bounds__(NT) void k_div_fftx(Batch B)
     const int pair0 = blockIdx.x * LP;
     const double idx = D.idx, idy = D.idy, idz = D.idz;
     const long long sxy = (long long)N * ny;
-    for (int e = tid; e < LP * N; e += NT) {
-        const int lp = e / N, i = e - lp * N;
-        const int pair = pair0 + lp;
-        double r2[2] = {0.0, 0.0};
-        if (pair < npairs) {
+    // divergence of u* on the block's lines; loads of two elements (12 values) are issued
+    // before their arithmetic and LDS stores
+    constexpr int M = (LP * N + NT - 1) / NT, G = M < 2 ? M : 2;
+    const bool walls = D.walls != 0;
+#pragma unroll
+    for (int g0 = 0; g0 < M; g0 += G) {
+        double ld[G][2][7];
+        int slot[G];
+#pragma unroll
+        for (int m = 0; m < G; ++m) {
+            const int e = tid + (g0 + m) * NT;
+            const int ee = e < LP * N ? e : 0;
+            const int lp = ee / N, i = ee - lp * N;
+            const int pair = pair0 + lp;
+            slot[m] = (e < LP * N) ? ee : -1;
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
-                const int l = 2 * pair + h;
-                if (l < nlines) {
-                    const int k = l / ny, j = l - k * ny;
-                    const long long q = (long long)l * N + i;
-                    const double du = D.us[q] - D.us[q - i + wrapi(i - 1, N)];
-                    double vm;
-                    if (j > 0) vm = D.vs[q - N];
-                    else vm = D.walls ? 0.0 : D.vs[q + (long long)(ny - 1) * N];
-                    const double dv = D.vs[q] - vm;
-                    const double wm = (k > 0) ? D.ws[q - sxy] : D.ws[q + (long long)(nz - 1) * sxy];
-                    const double dw = D.ws[q] - wm;
-                    r2[h] = sc * (du * idx + dv * idy + dw * idz);
-                }
+                int l = 2 * pair + h;
+                const bool ok = pair < npairs && l < nlines;
+                l = ok ? l : 0;
+                const int k = l / ny, j = l - k * ny;
+                const long long q = (long long)l * N + i;
+                ld[m][h][0] = D.us[q];
+                ld[m][h][1] = D.us[q - i + wrapi(i - 1, N)];
+                ld[m][h][2] = D.vs[q];
+                ld[m][h][3] = (j > 0) ? D.vs[q - N] : D.vs[q + (long long)(ny - 1) * N];
+                ld[m][h][4] = D.ws[q];
+                ld[m][h][5] = (k > 0) ? D.ws[q - sxy] : D.ws[q + (long long)(nz - 1) * sxy];
+                ld[m][h][6] = (ok ? 1.0 : 0.0) * ((j == 0 && walls) ? 0.0 : 1.0);   // flags
+                if (!ok) ld[m][h][6] = -1.0;
             }
         }
-        buf[lp * N + i] = make_double2(r2[0], r2[1]);
+#pragma unroll
+        for (int m = 0; m < G; ++m) {
+            if (slot[m] < 0) continue;
+            double r2[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const double* a = ld[m][h];
+                const double vm = (a[6] > 0.0) ? a[3] : 0.0;        // wall: v = 0 below row 0
+                const double rr = sc * ((a[0] - a[1]) * idx + (a[2] - vm) * idy + (a[4] - a[5]) * idz);
+                r2[h] = (a[6] < 0.0) ? 0.0 : rr;
+            }
+            buf[slot[m]] = make_double2(r2[0], r2[1]);
+        }
     }
     __syncthreads();
     const int lp = tid / T, t = tid - (tid / T) * T;
@@ -106,22 +170,12 @@ __global__ __launch_bounds__(NT) void k_fft_strided(Batch B, int axis)
     long long base, es;
     if (axis == 1) { base = (long long)other * ny * nh + kx0; es = nh; }
     else { base = (long long)other * nh + kx0; es = (long long)nh * ny; }
-    for (int e = tid; e < N * TK; e += NT) {
-        const int n = e / TK, c = e - n * TK;
-        double2 x = make_double2(0.0, 0.0);
-        if (kx0 + c < nh) x = D.spec[base + n * es + c];
-        buf[e] = INV ? cconj(x) : x;
-    }
+    const bool colok = kx0 + tid % TK < nh;
+    tile_in<N, INV>(buf, D.spec + base, es, colok, tid);
     __syncthreads();
     const int c = tid % TK, t = tid / TK;
     fft_stages<N, T, 0, 1>(buf + c, TK, t, t < T, tw);
-    for (int e = tid; e < N * TK; e += NT) {
-        const int n = e / TK, cc = e - n * TK;
-        if (kx0 + cc < nh) {
-            const double2 x = buf[e];
-            D.spec[base + n * es + cc] = INV ? cconj(x) : x;
-        }
-    }
+    tile_out<N, INV>(buf, D.spec + base, es, colok, tid);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -141,10 +195,8 @@ __global__ __launch_bounds__(NT) void k_solve_periodic(Batch B)
     const int tile = blockIdx.x % ntk, ky = blockIdx.x / ntk;
     const int kx0 = tile * TK;
     const long long base = (long long)ky * nh + kx0, es = (long long)nh * ny;
-    for (int e = tid; e < N * TK; e += NT) {
-        const int n = e / TK, c = e - n * TK;
-        buf[e] = (kx0 + c < nh) ? D.spec[base + n * es + c] : make_double2(0.0, 0.0);
-    }
+    const bool colok = kx0 + tid % TK < nh;
+    tile_in<N, false>(buf, D.spec + base, es, colok, tid);
     __syncthreads();
     const int c = tid % TK, t = tid / TK;
     fft_stages<N, T, 0, 1>(buf + c, TK, t, t < T, tw);
@@ -163,10 +215,7 @@ __global__ __launch_bounds__(NT) void k_solve_periodic(Batch B)
     }
     __syncthreads();
     fft_stages<N, T, 0, 1>(buf + c, TK, t, t < T, tw);
-    for (int e = tid; e < N * TK; e += NT) {
-        const int n = e / TK, cc = e - n * TK;
-        if (kx0 + cc < nh) D.spec[base + n * es + cc] = cconj(buf[e]);
-    }
+    tile_out<N, true>(buf, D.spec + base, es, colok, tid);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -265,21 +314,39 @@ __global__ __launch_bounds__(NT) void k_ifftx(Batch B)
     const int npairs = (nlines + 1) >> 1;
     const int pair0 = blockIdx.x * LP;
     const int nh = D.nh;
-    for (int e = tid; e < LP * N; e += NT) {
-        const int lp = e / N, n = e - lp * N;
-        const int pair = pair0 + lp;
-        double2 Z = make_double2(0.0, 0.0);
-        if (pair < npairs) {
-            const int la = 2 * pair;
-            const bool hasb = la + 1 < nlines;
-            const bool lo = n <= N / 2;
-            const int k = lo ? n : N - n;
-            double2 a = D.spec[(long long)la * nh + k];
-            double2 b = hasb ? D.spec[(long long)(la + 1) * nh + k] : make_double2(0.0, 0.0);
-            if (!lo) { a = cconj(a); b = cconj(b); }
-            Z = make_double2(a.x - b.y, a.y + b.x);   // a + i b
+    // Hermitian extension of two half spectra into one complex line; loads of four elements are
+    // issued before their LDS stores
+    constexpr int M = (LP * N + NT - 1) / NT, G = M < 4 ? M : 4;
+#pragma unroll
+    for (int g0 = 0; g0 < M; g0 += G) {
+        double2 av[G], bv[G];
+#pragma unroll
+        for (int m = 0; m < G; ++m) {
+            const int e = tid + (g0 + m) * NT;
+            const int ee = e < LP * N ? e : 0;
+            const int lp = ee / N, n = ee - lp * N;
+            const int pair = pair0 + lp;
+            const int la = pair < npairs ? 2 * pair : 0;
+            const int lb = (pair < npairs && la + 1 < nlines) ? la + 1 : la;
+            const int k = n <= N / 2 ? n : N - n;
+            av[m] = D.spec[(long long)la * nh + k];
+            bv[m] = D.spec[(long long)lb * nh + k];
         }
-        buf[e] = cconj(Z);
+#pragma unroll
+        for (int m = 0; m < G; ++m) {
+            const int e = tid + (g0 + m) * NT;
+            if (e >= LP * N) continue;
+            const int lp = e / N, n = e - lp * N;
+            const int pair = pair0 + lp;
+            double2 Z = make_double2(0.0, 0.0);
+            if (pair < npairs) {
+                double2 a = av[m];
+                double2 b = (2 * pair + 1 < nlines) ? bv[m] : make_double2(0.0, 0.0);
+                if (n > N / 2) { a = cconj(a); b = cconj(b); }
+                Z = make_double2(a.x - b.y, a.y + b.x);   // a + i b
+            }
+            buf[e] = cconj(Z);
+        }
     }
     __syncthreads();
     const int lp = tid / T, t = tid - (tid / T) * T;
