@@ -39,6 +39,8 @@ def _args():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=0, help="oracle steps (0 = size to ~15 s)")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=500)
     ap.add_argument("--quiet", action="store_true")
     return ap.parse_args()
 
@@ -85,6 +87,25 @@ def run_gpu(wl, precision, steps, warmup, quiet):
     h = G.health()
     G.close()
     return {"ms": ms, "wall_s": wall, "prof": prof, "health": h}
+
+
+def serving(n_requests, quiet):
+    """Rheology sweep served with continuous batching: a burst run (all requests at t = 0) gives
+    the saturated throughput; a Poisson run at 0.7 of that request rate gives latencies."""
+    from paper_1803_09563_amd.serving import Server, make_requests
+    burst = Server(budget_bytes=200e9).run(make_requests(n_requests, rate=None), time_limit=600)
+    _log(f"serving burst: {burst}", quiet)
+    rate = 0.7 * n_requests / burst["makespan_s"]
+    pois = Server(budget_bytes=200e9).run(make_requests(n_requests, rate=rate), time_limit=600)
+    _log(f"serving poisson: {pois}", quiet)
+    return {"requests": n_requests, "precision": "mixed", "hbm_budget_bytes": 200e9,
+            "saturated_cell_steps_per_s": burst["cell_steps_per_s"],
+            "burst_makespan_s": burst["makespan_s"], "burst_p50_s": burst["p50_latency_s"],
+            "burst_p99_s": burst["p99_latency_s"],
+            "poisson_rate_per_s": rate, "p50_latency_s": pois["p50_latency_s"],
+            "p99_latency_s": pois["p99_latency_s"], "cell_steps_per_s": pois["cell_steps_per_s"],
+            "peak_active": pois["peak_active"], "peak_hbm_bytes": pois["peak_hbm_bytes"],
+            "errors": burst["errors"] + pois["errors"]}
 
 
 def cpu_baseline(wl, steps, quiet):
@@ -173,6 +194,8 @@ def main():
                         "predictor_avg_us": mpred * 1e3,
                         "predictor_hbm_frac": PRED_BYTES["mixed"] * wl.ncell / (mpred * 1e-3) / 1e9 / HBM_PEAK_GBS,
                         "step_hbm_frac": STEP_BYTES["mixed"] * mv / 1e9 / HBM_PEAK_GBS}
+    if not a.no_serving:
+        out["serving"] = serving(a.serving_requests, a.quiet)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, a.cpu_steps, a.quiet)
     print(json.dumps(out), flush=True)

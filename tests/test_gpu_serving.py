@@ -1,0 +1,74 @@
+"""Serving loop: continuous batching over the C-ABI.  Each request's result is bitwise the same
+alone and in the mix; the HBM budget and slot caps bind; a request that blows up (NaN) is retired
+with an error without touching the others."""
+import numpy as np
+import pytest
+
+from paper_1803_09563_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _requests(n=10, seed=7, steps=(20, 60), sizes=(32, 48)):
+    from paper_1803_09563_amd.serving import make_requests
+    reqs = make_requests(n, rate=None, seed=seed, step_range=steps, sizes=sizes)
+    for i, r in enumerate(reqs):
+        r.arrival = 0.002 * i            # staggered: later requests join running batches
+    return reqs
+
+
+def _alone(wl):
+    import torch
+    import paper_1803_09563_amd as evp
+    from paper_1803_09563_amd.serving import device_initial_fields
+    G = evp.Grid(wl.nx, wl.ny, wl.nz, wl.lx, wl.ly, wl.lz, walls=wl.walls,
+                 precision=evp.MIXED if wl.precision == "mixed" else evp.FP64)
+    G.set_rheology(**wl.rheology())
+    G.set_forcing(*wl.force)
+    G.write_fields(*device_initial_fields(wl))
+    G.project()
+    G.step(wl.dt, wl.steps)
+    out = G.read_fields(("u", "v", "w", "p", "B"))
+    torch.cuda.synchronize()
+    return {k: t.cpu().numpy() for k, t in out.items()}, G.health()
+
+
+def test_results_identical_alone_and_in_the_mix():
+    from paper_1803_09563_amd.serving import Server
+    reqs = _requests()
+    stats = Server(keep_fields=True, chunk=7).run(reqs, time_limit=120)
+    assert stats["requests"] == len(reqs) and stats["errors"] == 0
+    assert stats["launches"] < sum(-(-r.wl.steps // 7) for r in reqs)   # batching happened
+    for r in reqs:
+        ref, _ = _alone(r.wl)
+        for k in ("u", "v", "w", "p", "B"):
+            assert np.array_equal(ref[k], r.fields[k]), (r.rid, k)
+    assert stats["p99_latency_s"] >= stats["p50_latency_s"] > 0
+
+
+def test_budget_and_slots_bind():
+    import paper_1803_09563_amd as evp
+    from paper_1803_09563_amd.serving import Server
+    reqs = _requests(n=8, seed=11)
+    for r in reqs:
+        r.arrival = 0.0
+    per = max(evp.workspace_bytes(r.wl.nx, r.wl.ny, r.wl.nz, False, evp.MIXED) for r in reqs)
+    srv = Server(budget_bytes=2.5 * per, max_active=3, chunk=10)
+    stats = srv.run(reqs, time_limit=120)
+    assert stats["requests"] == 8 and stats["errors"] == 0
+    assert stats["peak_active"] <= 3 and stats["peak_hbm_bytes"] <= 2.5 * per
+
+
+def test_failure_is_isolated():
+    from paper_1803_09563_amd.serving import Server
+    reqs = _requests(n=6, seed=5)
+    bad = reqs[2]
+    bad.wl.extra = dict(bad.wl.extra, inject_nan=True)
+    Server(keep_fields=True, chunk=5).run(reqs, time_limit=120)
+    assert bad.status == "error"
+    for r in reqs:
+        if r is bad:
+            continue
+        assert r.status == "done"
+        ref, _ = _alone(r.wl)
+        assert np.array_equal(ref["u"], r.fields["u"]) and np.array_equal(ref["B"], r.fields["B"])
