@@ -68,6 +68,12 @@ __device__ __forceinline__ T weno5u(T v1, T v2, T v3, T v4, T v5, T eps2)
     T e2 = eps2 + c13 * a * a + q * b * b;
     a = v3 - (T)2 * v4 + v5; b = (T)3 * v3 - (T)4 * v4 + v5;
     T e3 = eps2 + c13 * a * a + q * b * b;
+    if constexpr (sizeof(T) == 4) {
+        // FP32: eps h^2 squared twice in the common denominator underflows on fine grids; the
+        // weights are invariant under a common scale, so normalise by the largest indicator
+        const T im = fast_rcp(fmaxf(fmaxf(e1, e2), e3));
+        e1 *= im; e2 *= im; e3 *= im;
+    }
     e1 *= e1; e2 *= e2; e3 *= e3;
     const T w1 = (T)0.1 * e2 * e3, w2 = (T)0.6 * e1 * e3, w3 = (T)0.3 * e1 * e2;
     return (w1 * p1 + w2 * p2 + w3 * p3) * fast_rcp(w1 + w2 + w3);

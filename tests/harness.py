@@ -65,8 +65,10 @@ def field_errors(ref: dict, got: dict):
     return err
 
 
-def assert_close(ref, got, tol, what=""):
+def assert_close(ref, got, tol, what="", p_tol=None):
+    """All fields within tol; the pressure within p_tol (default tol)."""
     err = field_errors(ref, got)
-    bad = {k: v for k, v in err.items() if not (v <= tol)}
+    p_tol = tol if p_tol is None else p_tol
+    bad = {k: v for k, v in err.items() if not (v <= (p_tol if k == "p" else tol))}
     assert not bad, f"{what}: fields above {tol}: {bad} (all: {err})"
     return err

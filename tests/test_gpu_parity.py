@@ -139,6 +139,23 @@ def test_full_step_parity_100_steps(case):
     assert_close(oracle_state(s), gpu_state(G), 1e-10, f"{case}, 100 steps")
 
 
+def test_mixed_stage_fine_spacing():
+    """FP32 WENO weights on a fine grid near B = I (smoothness indicators ~ eps h^2): the
+    predictor stays finite and within the mixed tolerance of the FP64 oracle."""
+    import paper_1803_09563_amd as evp
+    wl = inputs.channel_fene_p(64, 256, 16, precision="mixed")
+    u, v, w, B = inputs.initial_fields(wl)
+    s = oracle_solver(wl)
+    s.write_fields(u, v, w, B)
+    s.step(wl.dt, 2, flags=oracle.Solver.STOP_AFTER_PREDICTOR)
+    G = gpu_grid(wl, precision=evp.MIXED)
+    G.write_fields(*to_dev(u, v, w, B))
+    G.step(wl.dt, 2, flags=2)
+    got = gpu_state(G, ("u", "v", "w", "B"))
+    assert all(np.isfinite(x).all() for x in got.values())
+    assert_close(oracle_state(s), got, 1e-4, "mixed fine spacing")
+
+
 @pytest.mark.parametrize("case", ["kolmogorov_saramito_48", "channel_fene_p_64x48x32"])
 def test_mixed_precision_error(case):
     import paper_1803_09563_amd as evp
@@ -155,7 +172,7 @@ def test_mixed_precision_error(case):
     G.write_fields(*to_dev(u, v, w, B))
     G.project()
     G.step(wl.dt, 200)
-    assert_close(oracle_state(s), gpu_state(G), 1e-4, f"mixed {case}, 200 steps")
+    assert_close(oracle_state(s), gpu_state(G), 1e-4, f"mixed {case}, 200 steps", p_tol=1e-3)
 
 
 def test_batch_equals_single_bitwise():
