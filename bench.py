@@ -30,6 +30,27 @@ PRED_BYTES = {"fp64": 24 + 6 * 8 * 4 + 3 * 8 * 2 + 24, "mixed": 24 + 6 * 4 * 4 +
 STEP_BYTES = {k: v + 32 + 48 + 72 for k, v in PRED_BYTES.items()}
 
 
+TRAFFIC_FILE = os.path.join(HERE, "profiles", "predictor_kolmogorov128_hbm_traffic.txt")
+PRED_SOURCE = os.path.join(HERE, "paper_1803_09563_amd", "csrc", "k_predictor_zm.hip")
+
+
+def measured_traffic(precision="double"):
+    """HBM bytes per predictor launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary,
+    or None if the kernel source changed since the counters were taken (or no summary exists)."""
+    import hashlib
+    import re
+    try:
+        text = open(TRAFFIC_FILE).read()
+        sha = hashlib.sha256(open(PRED_SOURCE, "rb").read()).hexdigest()[:16]
+    except OSError:
+        return None
+    m = re.search(r"sha256\[:16\] = ([0-9a-f]{16})", text)
+    t = re.search(rf"traffic_bytes_per_launch_{precision} = (\d+)", text)
+    if not m or not t or m.group(1) != sha:
+        return None
+    return int(t.group(1))
+
+
 def _args():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -179,7 +200,8 @@ def main():
                    "rheology": "Saramito Wi=1 Bi=0.5 beta=0.5 Re=1000", "dt": wl.dt,
                    "precision": "fp64"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic("double") if a.n == 128 else None,
                      "kernel": "predictor (fused stress + momentum stencil)",
                      "bytes_per_cell": PRED_BYTES["fp64"], "avg_launch_us": pred_ms * 1e3},
         "step_hbm_frac": STEP_BYTES["fp64"] * value / 1e9 / HBM_PEAK_GBS,
