@@ -281,12 +281,26 @@ int enqueue_steps(evp_grid* const* gs, int count, double dt, int nsteps, unsigne
             b.dt[i] = dt;
             b.state[i] = gs[i]->parity | (gs[i]->have_hist ? 0 : evp::ST_EULER);
         }
-        int r = timed(g0, EVP_K_PREDICTOR, [&] {
-            return use_reference_predictor()
-                       ? evp::launch_predictor_ref(b, g0->precision, g0->nx, g0->ny, g0->nz, freeze, g0->stream)
-                       : evp::launch_predictor_zm(b, g0->precision, g0->nx, g0->ny, g0->nz, freeze, g0->stream,
-                                                  g0->bc == EVP_WALLS);
-        });
+        // the predictor is specialised per constitutive model: one launch per model present, so
+        // a grid's arithmetic is the same alone and in any batch
+        int r = EVP_OK;
+        for (int model = EVP_OLDROYD_B; model <= EVP_SARAMITO && !r; ++model) {
+            Batch bm{};
+            for (int i = 0; i < count; ++i)
+                if (gs[i]->h.model == model) {
+                    bm.d[bm.count] = b.d[i];
+                    bm.dt[bm.count] = b.dt[i];
+                    bm.state[bm.count] = b.state[i];
+                    bm.count++;
+                }
+            if (bm.count == 0) continue;
+            r = timed(g0, EVP_K_PREDICTOR, [&] {
+                return use_reference_predictor()
+                           ? evp::launch_predictor_ref(bm, g0->precision, g0->nx, g0->ny, g0->nz, freeze, g0->stream)
+                           : evp::launch_predictor_zm(bm, g0->precision, g0->nx, g0->ny, g0->nz, freeze,
+                                                      g0->stream, g0->bc == EVP_WALLS, model);
+            });
+        }
         if (r) return r;
         if (stop && !freeze) {
             hipError_t e = evp::launch_copy_ustar(b, g0->nx, g0->ny, g0->nz, true, g0->stream);

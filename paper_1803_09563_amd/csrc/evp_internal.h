@@ -51,7 +51,7 @@ constexpr int ST_EULER = 2;
 hipError_t launch_predictor_ref(const Batch& b, int precision, int nx, int ny, int nz, bool freeze,
                                 hipStream_t s);
 hipError_t launch_predictor_zm(const Batch& b, int precision, int nx, int ny, int nz, bool freeze,
-                               hipStream_t s, bool walls);
+                               hipStream_t s, bool walls, int model);
 int predictor_chunk(int nx, int ny, int nz);
 hipError_t launch_div_fftx(const Batch& b, int nx, int ny, int nz, hipStream_t s);
 hipError_t launch_fft_strided(const Batch& b, int nx, int ny, int nz, int axis, bool inverse,

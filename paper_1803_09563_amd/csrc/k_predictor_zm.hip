@@ -91,7 +91,7 @@ __device__ __forceinline__ T weno_up(T f0, T f1, T f2, T f3, T f4, T f5, T f6, T
     return weno5u<T>(v1, v2, v3, v4, v5, eps2);
 }
 
-template <typename T, bool WALLS>
+template <typename T, bool WALLS, int MODEL>
 __global__ __launch_bounds__(NTH, 2) void k_pred_zm(Batch B, int freeze, int kc)
 {
     __shared__ Smem<T> S;
@@ -121,7 +121,7 @@ __global__ __launch_bounds__(NTH, 2) void k_pred_zm(Batch B, int freeze, int kc)
     const bool euler = (st & ST_EULER) != 0;
     const T dt = (T)B.dt[b];
     const T c1 = euler ? (T)1 : (T)1.5, c2 = euler ? (T)0 : (T)-0.5;
-    const bool fene = D.model == EVP_FENE_P, sara = D.model == EVP_SARAMITO;
+    constexpr bool fene = MODEL == EVP_FENE_P, sara = MODEL == EVP_SARAMITO;
     const T G = (T)D.G, L2 = (T)D.L2, afene = (T)D.a_fene, il = (T)D.inv_lam, tyld = (T)D.tau_y;
     const T idx = (T)D.idx, idy = (T)D.idy, idz = (T)D.idz;
     const T e2x = (T)(1e-6 * D.dx * D.dx), e2y = (T)(1e-6 * D.dy * D.dy), e2z = (T)(1e-6 * D.dz * D.dz);
@@ -468,19 +468,26 @@ int predictor_chunk(int nx, int ny, int nz)
 }
 
 hipError_t launch_predictor_zm(const Batch& b, int precision, int nx, int ny, int nz, bool freeze,
-                               hipStream_t s, bool walls)
+                               hipStream_t s, bool walls, int model)
 {
     const int kc = predictor_chunk(nx, ny, nz);
     const int nblk = ((nx + TX - 1) / TX) * ((ny + TY - 1) / TY) * ((nz + kc - 1) / kc);
     dim3 grid(nblk, b.count);
     const int fz = freeze ? 1 : 0;
-    if (precision == EVP_MIXED) {
-        if (walls) hipLaunchKernelGGL((k_pred_zm<float, true>), grid, dim3(NTH), 0, s, b, fz, kc);
-        else hipLaunchKernelGGL((k_pred_zm<float, false>), grid, dim3(NTH), 0, s, b, fz, kc);
-    } else {
-        if (walls) hipLaunchKernelGGL((k_pred_zm<double, true>), grid, dim3(NTH), 0, s, b, fz, kc);
-        else hipLaunchKernelGGL((k_pred_zm<double, false>), grid, dim3(NTH), 0, s, b, fz, kc);
+#define EVP_LAUNCH(TT, WW, MM) hipLaunchKernelGGL((k_pred_zm<TT, WW, MM>), grid, dim3(NTH), 0, s, b, fz, kc)
+#define EVP_BY_MODEL(TT, WW)                                                                       \
+    switch (model) {                                                                               \
+    case EVP_FENE_P: EVP_LAUNCH(TT, WW, EVP_FENE_P); break;                                       \
+    case EVP_SARAMITO: EVP_LAUNCH(TT, WW, EVP_SARAMITO); break;                                   \
+    default: EVP_LAUNCH(TT, WW, EVP_OLDROYD_B); break;                                            \
     }
+    if (precision == EVP_MIXED) {
+        if (walls) { EVP_BY_MODEL(float, true) } else { EVP_BY_MODEL(float, false) }
+    } else {
+        if (walls) { EVP_BY_MODEL(double, true) } else { EVP_BY_MODEL(double, false) }
+    }
+#undef EVP_BY_MODEL
+#undef EVP_LAUNCH
     return hipGetLastError();
 }
 
