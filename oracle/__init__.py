@@ -4,7 +4,8 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of ``b
 this package.  It shares no code with the HIP path (``paper_1803_09563_amd``) and never imports it.
 
 A plain, slow FP64 CPU implementation of one time step of the paper's single-phase Eulerian
-solver (Izbassarov et al., Sec. 3.2.2 "Time integration: Adams-Bashforth scheme"):
+solver (Izbassarov et al., Sec. 3.2.2 "Time integration: Adams-Bashforth scheme", and the
+Runge-Kutta alternative of Sec. 3.3.1, ``Solver.step_rk3``):
 
 * predictor -- Eqs. (ab2tau), (ab2), (rt), (ru) with the closures of Table 1 -- in plain C loops
   (``evp_oracle.c``), loaded through ctypes;
@@ -83,6 +84,8 @@ def _load():
         lib.oracle_stress.restype = None
         lib.oracle_closure.argtypes = [pp, dp, dp, dp]
         lib.oracle_closure.restype = None
+        lib.oracle_terms.argtypes = [pp, dp, dp, dp, dp, dp, dp, dp, dp]
+        lib.oracle_terms.restype = None
         _lib = lib
     return _lib
 
@@ -271,6 +274,41 @@ def project(g: Grid, us, vs, ws, dt: float, rho: float = 1.0):
 
 
 # ----------------------------------------------------------------------------------------------
+# Terms of the Runge-Kutta integrator (Sec. 3.3.1)
+# ----------------------------------------------------------------------------------------------
+
+# Eq. (eq:RK): alpha, zeta, xi of the three substeps
+RK3_ALPHA = (4.0 / 15.0, 1.0 / 15.0, 1.0 / 6.0)
+RK3_ZETA = (8.0 / 15.0, 5.0 / 12.0, 3.0 / 4.0)
+RK3_XI = (0.0, -17.0 / 60.0, -5.0 / 12.0)
+
+
+def terms(g: Grid, r: Rheology, u, v, w, B, forcing=(FORCE_NONE, 0.0, 0.0),
+          walls_uv=(0.0, 0.0, 0.0, 0.0)):
+    """At one state: RT (bracket of Eq. RK-rt, 6 planes), and on the faces A = div(uu),
+    V = mu_s lap u, T = div(tau) (3 planes each)."""
+    shp = g.shape
+    RT = np.empty((6,) + shp); A = np.empty((3,) + shp)
+    V = np.empty((3,) + shp); T = np.empty((3,) + shp)
+    p = _params(g, r, forcing, walls_uv)
+    arrs = [np.ascontiguousarray(x, dtype=np.float64) for x in (u, v, w, B)]
+    _load().oracle_terms(ctypes.byref(p), *[_ptr(x) for x in arrs], _ptr(RT), _ptr(A), _ptr(V),
+                         _ptr(T))
+    return RT, A, V, T
+
+
+def body_force(g: Grid, forcing):
+    """f on the faces (3 planes): f_x = amp or amp sin(ky y) on the x-faces, zero elsewhere."""
+    f = np.zeros((3,) + g.shape)
+    kind, amp, ky = forcing
+    if kind == FORCE_CONST_X:
+        f[0] = amp
+    elif kind == FORCE_SIN_X_OF_Y:
+        f[0] = (amp * np.sin(ky * g.yc()))[None, :, None]
+    return f
+
+
+# ----------------------------------------------------------------------------------------------
 # The whole step
 # ----------------------------------------------------------------------------------------------
 
@@ -344,6 +382,49 @@ class Solver:
             if flags & self.FREEZE_VELOCITY:
                 continue
             self.u, self.v, self.w, self.p = project(self.g, us, vs, ws, dt, self.r.rho)
+
+    def step_rk3(self, dt: float, nsteps: int = 1, flags: int = 0):
+        """Low-storage three-substep Runge-Kutta step of Sec. 3.3.1.  Per substep k:
+        B^k = B^{k-1} + dt (zeta RT^{k-1} + xi RT^{k-2})                         (Eqs. RK-rt, rk3tau)
+        u*  = u^{k-1} + dt [-zeta A^{k-1} - xi A^{k-2} - 2 alpha grad p^{k-1} / rho
+                            + (2 alpha V^{k-1} + alpha (T^k + T^{k-1}) + 2 alpha f) / rho]
+                                                                              (Eqs. NS-num1, rk3)
+        L psi = rho div(u*) / (2 alpha dt);  p^k = p^{k-1} + psi;
+        u^k = u* - 2 alpha dt grad(psi) / rho                                  (Eqs. NS-num2, NS-num3)
+        The viscous term is taken explicitly at k-1 with weight 2 alpha (the paper's superscript k
+        on it would need an implicit solve it does not describe); the stress divergence uses
+        B^k, known from the stress update of the same substep."""
+        g, rh = self.g, self.r
+        rho = rh.rho
+        f = body_force(g, self.forcing)
+        for _ in range(nsteps):
+            RT2 = A2 = None
+            for kk in range(3):
+                al, ze, xi = RK3_ALPHA[kk], RK3_ZETA[kk], RK3_XI[kk]
+                RT1, A1, V1, T1 = terms(g, rh, self.u, self.v, self.w, self.B, self.forcing,
+                                        self.walls_uv)
+                Bk = self.B + dt * (ze * RT1 + (xi * RT2 if RT2 is not None else 0.0))
+                if flags & self.FREEZE_VELOCITY:
+                    self.B = Bk
+                    RT2 = RT1
+                    continue
+                _, _, _, Tk = terms(g, rh, self.u, self.v, self.w, Bk, self.forcing, self.walls_uv)
+                gx, gy, gz = gradient(g, self.p)
+                G = np.stack([gx, gy, gz])
+                RU = -ze * A1 - (xi * A2 if A2 is not None else 0.0) - 2 * al * G / rho \
+                    + (2 * al * V1 + al * (Tk + T1) + 2 * al * f) / rho
+                us = self.u + dt * RU[0]
+                vs = self.v + dt * RU[1]
+                ws = self.w + dt * RU[2]
+                if g.walls:
+                    vs[:, -1, :] = 0.0
+                dte = 2 * al * dt
+                u, v, w, psi = project(g, us, vs, ws, dte, rho)
+                self.u, self.v, self.w = u, v, w
+                self.p = self.p + psi
+                self.B = Bk
+                RT2, A2 = RT1, A1
+            self.nstep += 1
 
     def stress(self):
         return stress(self.g, self.r, self.B)

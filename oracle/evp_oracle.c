@@ -281,14 +281,15 @@ static double force_x(const oracle_params* P, int j)
     return 0.0;
 }
 
-/* Momentum right-hand side RU of Eq. (ru) (rho constant, g = 0, no surface tension) on the
- * three faces owned by cell (i,j,k): divergence-form advection, mu_s times the 7-point
- * Laplacian, the divergence of the extra stress from centre and edge-averaged values, and f. */
-static void momentum_rhs(const oracle_params* P, const double* u, const double* v, const double* w,
-                         const double* B, int i, int j, int k, double ru[3])
+/* The three momentum terms of Eq. (ru) on the three faces owned by cell (i,j,k): A =
+ * divergence-form advection div(uu), Vv = mu_s times the 7-point Laplacian, T = divergence of the
+ * extra stress from centre and edge-averaged values.  The top wall face of a channel gets 0. */
+static void momentum_parts(const oracle_params* P, const double* u, const double* v,
+                           const double* w, const double* B, int i, int j, int k, double A[3],
+                           double Vv[3], double T[3])
 {
     const double dx = P->dx, dy = P->dy, dz = P->dz;
-    const double ms = P->mu_s, rho = P->rho;
+    const double ms = P->mu_s;
     double t00[6], t[6];
 
     /* ---- x-face (i+1/2, j, k) ---- */
@@ -330,12 +331,12 @@ static void momentum_rhs(const oracle_params* P, const double* u, const double* 
         stress_at(P, B, i + 1, j, k - 1, t); s[1] = t[XZ];
         e_bk = 0.25 * (t00[XZ] + s[0] + s[1] + s[2]);
         double divt = dtxx + (e_top - e_bot) / dy + (e_fr - e_bk) / dz;
-        ru[0] = -adv + (ms * lap + divt + force_x(P, j)) / rho;
+        A[0] = adv; Vv[0] = ms * lap; T[0] = divt;
     }
 
     /* ---- y-face (i, j+1/2, k) ---- */
     if (P->walls && j == P->ny - 1) {
-        ru[1] = 0.0;   /* top wall face: no penetration */
+        A[1] = 0.0; Vv[1] = 0.0; T[1] = 0.0;   /* top wall face: no penetration */
     } else {
         double vcT = 0.5 * (V(P, v, i, j, k) + V(P, v, i, j + 1, k));
         double vcB = 0.5 * (V(P, v, i, j - 1, k) + V(P, v, i, j, k));
@@ -372,7 +373,7 @@ static void momentum_rhs(const oracle_params* P, const double* u, const double* 
         stress_at(P, B, i, j + 1, k - 1, t); s[1] = t[YZ];
         eK = 0.25 * (t00[YZ] + s[0] + s[1] + s[2]);
         double divt = (eR - eL) / dx + dtyy + (eF - eK) / dz;
-        ru[1] = -adv + (ms * lap + divt) / rho;
+        A[1] = adv; Vv[1] = ms * lap; T[1] = divt;
     }
 
     /* ---- z-face (i, j, k+1/2) ---- */
@@ -412,8 +413,20 @@ static void momentum_rhs(const oracle_params* P, const double* u, const double* 
         stress_at(P, B, i, j - 1, k + 1, t); s[1] = t[YZ];
         eB = 0.25 * (t00[YZ] + s[0] + s[1] + s[2]);
         double divt = (eR - eL) / dx + (eT - eB) / dy + dtzz;
-        ru[2] = -adv + (ms * lap + divt) / rho;
+        A[2] = adv; Vv[2] = ms * lap; T[2] = divt;
     }
+}
+
+/* Momentum right-hand side RU of Eq. (ru) (rho constant, g = 0, no surface tension):
+ * RU = -A + (Vv + T + f)/rho, with the body force f on the x-faces. */
+static void momentum_rhs(const oracle_params* P, const double* u, const double* v, const double* w,
+                         const double* B, int i, int j, int k, double ru[3])
+{
+    double A[3], Vv[3], T[3];
+    momentum_parts(P, u, v, w, B, i, j, k, A, Vv, T);
+    ru[0] = -A[0] + (Vv[0] + T[0] + force_x(P, j)) / P->rho;
+    ru[1] = -A[1] + (Vv[1] + T[1]) / P->rho;
+    ru[2] = -A[2] + (Vv[2] + T[2]) / P->rho;
 }
 
 /*
@@ -456,4 +469,33 @@ void oracle_predictor(const oracle_params* P, const double* u, const double* v, 
             }
         }
     }
+}
+
+/*
+ * Exported for the Runge-Kutta integrator of Sec. 3.3.1: the separate terms of Eqs. (RK-rt) and
+ * (NS-num1) at one state, on every cell.
+ *   RT: the bracket of Eq. (RK-rt) (the right-hand side of Eq. SRM2), six planes;
+ *   A : the advection term div(uu) on the three faces of each cell, three planes;
+ *   V : mu_s times the 7-point Laplacian of the face velocities, three planes;
+ *   T : div(tau) on the faces (centre and edge-averaged stresses), three planes.
+ * The top wall face of a channel gets 0 in A, V and T.
+ */
+void oracle_terms(const oracle_params* P, const double* u, const double* v, const double* w,
+                  const double* B, double* RT, double* A, double* V, double* T)
+{
+    const int nx = P->nx, ny = P->ny, nz = P->nz;
+    const size_t n = (size_t)nx * ny * nz;
+    #pragma omp parallel for schedule(static)
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                const size_t q = at(P, i, j, k);
+                double rt[6], a[3], vv[3], t[3];
+                stress_rhs(P, u, v, w, B, i, j, k, rt);
+                for (int c = 0; c < 6; ++c) RT[c * n + q] = rt[c];
+                momentum_parts(P, u, v, w, B, i, j, k, a, vv, t);
+                for (int c = 0; c < 3; ++c) {
+                    A[c * n + q] = a[c]; V[c * n + q] = vv[c]; T[c * n + q] = t[c];
+                }
+            }
 }
