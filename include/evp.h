@@ -10,7 +10,9 @@
  *     second-order central differences; fifth-order WENO for u.grad(B), Sec. 3.1);
  *   - the Adams-Bashforth step and Chorin projection of Sec. 3.2.2, Eqs. (ab2tau), (ab2), (rt),
  *     (ru), (var poisson), (projection), with constant rho, g = 0 and f a body force; the pressure
- *     equation is solved with FFTs in periodic directions and a tridiagonal solve across walls.
+ *     equation is solved with FFTs in periodic directions and a tridiagonal solve across walls;
+ *   - alternatively the low-storage three-substep Runge-Kutta step of Sec. 3.3.1, Eqs. (RK-rt),
+ *     (NS-num1), (rk3tau), (rk3), (NS-num2), (NS-num3), with the coefficients of Eq. (RK).
  *
  * Conventions shared by every call
  *   - Status: 0 (EVP_OK) or a negative EVP_ERR_* code.  No call throws, aborts or prints;
@@ -41,7 +43,8 @@ extern "C" {
 #define EVP_ERR_ARG       -1   /* bad size, spacing, parameter, pointer or flag */
 #define EVP_ERR_WORKSPACE -2   /* workspace too small or not 256-byte aligned */
 #define EVP_ERR_STATE     -3   /* step/project/read before set_rheology or write_fields */
-#define EVP_ERR_SHAPE     -4   /* grids of one batch differ in shape, precision or stream */
+#define EVP_ERR_SHAPE     -4   /* grids of one batch differ in shape, precision, stream or
+                                  time integrator */
 #define EVP_ERR_HIP       -5   /* a HIP runtime call or kernel launch failed */
 
 /* boundary condition in y */
@@ -62,10 +65,14 @@ extern "C" {
 #define EVP_FORCE_CONST_X    1 /* f_x = amp */
 #define EVP_FORCE_SIN_X_OF_Y 2 /* f_x = amp * sin(ky * y), sampled at the u-face y */
 
+/* time integrators (evp_set_integrator) */
+#define EVP_AB2 0              /* Adams-Bashforth, Sec. 3.2.2 (default) */
+#define EVP_RK3 1              /* low-storage Runge-Kutta, three substeps, Sec. 3.3.1 */
+
 /* evp_step flags */
 #define EVP_FREEZE_VELOCITY      1u  /* advance B only, u unchanged: the "uncoupled" shear test
                                         of Sec. 4.1.3 */
-#define EVP_STOP_AFTER_PREDICTOR 2u  /* skip the projection: u <- u* (stage check) */
+#define EVP_STOP_AFTER_PREDICTOR 2u  /* skip the projection: u <- u* (stage check; AB2 only) */
 
 /* evp_read_fields mask bits */
 #define EVP_READ_U    1u
@@ -86,7 +93,8 @@ extern "C" {
 #define EVP_K_FFT_INV   4      /* inverse transform along y (periodic) or z (walls) */
 #define EVP_K_IFFTX     5      /* inverse x transform -> p */
 #define EVP_K_CORRECT   6      /* u = u* - (dt/rho) grad p */
-#define EVP_K_COUNT     7
+#define EVP_K_STRESS_DIV 7     /* RK3: u* += dt (alpha/rho) div tau(B^k) */
+#define EVP_K_COUNT     8
 
 typedef struct evp_grid evp_grid;
 
@@ -149,13 +157,20 @@ int evp_write_fields(evp_grid* g, const double* u, const double* v, const double
  * projection with u* = u and dt = 1); p is set to the potential removed. */
 int evp_project(evp_grid* g);
 
-/* Advance nsteps steps of size dt > 0 (Sec. 3.2.2): predictor (stress transport, Eq. ab2tau;
- * momentum, Eq. ab2), then the Poisson solve and the velocity correction.  flags: EVP_FREEZE_*,
- * EVP_STOP_AFTER_PREDICTOR. */
+/* Time integrator of later evp_step calls: EVP_AB2 (default) or EVP_RK3.  A change of scheme
+ * clears the AB2 history, so the first AB2 step after RK3 steps is a forward-Euler start.  Host
+ * state only; enqueues nothing. */
+int evp_set_integrator(evp_grid* g, int scheme);
+
+/* Advance nsteps steps of size dt > 0.  AB2 (Sec. 3.2.2): predictor (stress transport, Eq.
+ * ab2tau; momentum, Eq. ab2), then the Poisson solve and the velocity correction.  RK3 (Sec.
+ * 3.3.1): three substeps k = 1, 2, 3, each B^k from Eq. (rk3tau), u* from Eq. (rk3) and the
+ * projection of Eqs. (NS-num2), (NS-num3) with 2 alpha_k dt; p is p^k = p^{k-1} + psi^k.  flags:
+ * EVP_FREEZE_VELOCITY, EVP_STOP_AFTER_PREDICTOR (AB2 only: EVP_ERR_ARG under RK3). */
 int evp_step(evp_grid* g, double dt, int nsteps, unsigned flags);
 
-/* The same for count <= EVP_MAX_BATCH grids of identical shape, boundary type, precision and
- * stream, each with its own rheology, forcing, walls and state: every kernel is launched once for
+/* The same for count <= EVP_MAX_BATCH grids of identical shape, boundary type, precision,
+ * stream and time integrator, each with its own rheology, forcing, walls and state: every kernel is launched once for
  * the whole batch.  Results are identical to count separate evp_step calls. */
 int evp_step_batch(evp_grid* const* grids, int count, double dt, int nsteps, unsigned flags);
 

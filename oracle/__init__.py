@@ -424,6 +424,7 @@ class Solver:
                 self.p = self.p + psi
                 self.B = Bk
                 RT2, A2 = RT1, A1
+            self.have_hist = False       # no AB2 history: a later AB2 step starts with Euler
             self.nstep += 1
 
     def stress(self):

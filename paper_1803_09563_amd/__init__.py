@@ -1,6 +1,7 @@
 """MI355X-native solver step for viscoelastic / elastoviscoplastic flow (Oldroyd-B, FENE-P,
 Saramito) on a uniform staggered grid: the single-phase Eulerian path of Izbassarov et al.,
-Sec. 3.2.2 (AB2 predictor + FFT/Thomas pressure projection).
+Sec. 3.2.2 (AB2 predictor + FFT/Thomas pressure projection), or the low-storage RK3 step of
+Sec. 3.3.1.
 
 This module is a thin ctypes binding of ``libevp.so`` (C-ABI in ``include/evp.h``).  It only
 marshals arguments: PyTorch provides device memory and the stream; every step of the method runs
@@ -15,7 +16,7 @@ import os
 __all__ = ["Grid", "step_batch", "EvpError", "lib", "workspace_bytes", "symbols",
            "OLDROYD_B", "FENE_P", "SARAMITO", "FP64", "MIXED", "PERIODIC", "WALLS",
            "FORCE_NONE", "FORCE_CONST_X", "FORCE_SIN_X_OF_Y", "FREEZE_VELOCITY",
-           "STOP_AFTER_PREDICTOR", "MAX_BATCH", "KERNEL_NAMES"]
+           "STOP_AFTER_PREDICTOR", "MAX_BATCH", "KERNEL_NAMES", "AB2", "RK3"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libevp.so")
@@ -24,10 +25,12 @@ PERIODIC, WALLS = 0, 1
 FP64, MIXED = 0, 1
 OLDROYD_B, FENE_P, SARAMITO = 0, 1, 2
 FORCE_NONE, FORCE_CONST_X, FORCE_SIN_X_OF_Y = 0, 1, 2
+AB2, RK3 = 0, 1
 FREEZE_VELOCITY, STOP_AFTER_PREDICTOR = 1, 2
 READ_U, READ_V, READ_W, READ_P, READ_B, READ_HIST = 1, 2, 4, 8, 16, 32
 MAX_BATCH = 32
-KERNEL_NAMES = ("predictor", "div_fftx", "fft_fwd", "solve", "fft_inv", "ifftx", "correct")
+KERNEL_NAMES = ("predictor", "div_fftx", "fft_fwd", "solve", "fft_inv", "ifftx", "correct",
+                "stress_div")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_1803_09563_amd/build.py` "
@@ -50,7 +53,7 @@ class _Health(ctypes.Structure):
 
 
 class _Profile(ctypes.Structure):
-    _fields_ = [("launches", ctypes.c_longlong * 7), ("ms", _d * 7)]
+    _fields_ = [("launches", ctypes.c_longlong * len(KERNEL_NAMES)), ("ms", _d * len(KERNEL_NAMES))]
 
 
 symbols = {
@@ -65,6 +68,7 @@ symbols = {
     "evp_set_walls": (_i, [_vp, _d, _d, _d, _d]),
     "evp_write_fields": (_i, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "evp_project": (_i, [_vp]),
+    "evp_set_integrator": (_i, [_vp, _i]),
     "evp_step": (_i, [_vp, _d, _i, ctypes.c_uint]),
     "evp_step_batch": (_i, [ctypes.POINTER(_vp), _i, _d, _i, ctypes.c_uint]),
     "evp_read_fields": (_i, [_vp, ctypes.c_uint, _vp, _vp, _vp, _vp, _vp, _vp]),
@@ -164,6 +168,12 @@ class Grid:
 
     def set_walls(self, u_bot=0.0, u_top=0.0, w_bot=0.0, w_top=0.0):
         _check(lib.evp_set_walls(self._h, u_bot, u_top, w_bot, w_top), "evp_set_walls")
+
+    def set_integrator(self, scheme):
+        """AB2 (Sec. 3.2.2, default) or RK3 (Sec. 3.3.1) for later steps; also "ab2" / "rk3"."""
+        if isinstance(scheme, str):
+            scheme = {"ab2": AB2, "rk3": RK3}[scheme.lower()]
+        _check(lib.evp_set_integrator(self._h, int(scheme)), "evp_set_integrator")
 
     def write_fields(self, u, v, w, B, hist=None):
         s = self.shape

@@ -1,5 +1,6 @@
 // Host side of libevp.so: argument checks, workspace carving, FP64 tables (twiddles, Laplacian
-// eigenvalues, Thomas pivots), the step schedule of Sec. 3.2.2 and per-kernel event timing.
+// eigenvalues, Thomas pivots), the step schedules of Sec. 3.2.2 (AB2) and Sec. 3.3.1 (RK3) and
+// per-kernel event timing.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -116,6 +117,7 @@ struct evp_grid {
     Desc h;            // host mirror of the device descriptor
     Desc* d;           // device descriptor
     int parity;
+    int integrator;    // EVP_AB2 or EVP_RK3
     bool have_hist, have_rheo, have_fields;
     long long nstep;
     bool prof;
@@ -268,8 +270,83 @@ int check_grid(evp_grid* g)
     return EVP_OK;
 }
 
+// Low-storage Runge-Kutta coefficients alpha, zeta, xi of the three substeps (Eq. RK)
+constexpr double kRkAlpha[3] = {4.0 / 15.0, 1.0 / 15.0, 1.0 / 6.0};
+constexpr double kRkZeta[3] = {8.0 / 15.0, 5.0 / 12.0, 3.0 / 4.0};
+constexpr double kRkXi[3] = {0.0, -17.0 / 60.0, -5.0 / 12.0};
+
+// The predictor launched once per constitutive model present in the batch, so a grid's
+// arithmetic is the same alone and in any batch.
+int predictor_by_model(evp_grid* const* gs, const Batch& b, bool freeze, bool rk3)
+{
+    evp_grid* g0 = gs[0];
+    int r = EVP_OK;
+    for (int model = EVP_OLDROYD_B; model <= EVP_SARAMITO && !r; ++model) {
+        Batch bm{};
+        for (int i = 0; i < 3; ++i) bm.rk[i] = b.rk[i];
+        for (int i = 0; i < b.count; ++i)
+            if (gs[i]->h.model == model) {
+                bm.d[bm.count] = b.d[i];
+                bm.dt[bm.count] = b.dt[i];
+                bm.state[bm.count] = b.state[i];
+                bm.count++;
+            }
+        if (bm.count == 0) continue;
+        r = timed(g0, EVP_K_PREDICTOR, [&] {
+            return use_reference_predictor()
+                       ? evp::launch_predictor_ref(bm, g0->precision, g0->nx, g0->ny, g0->nz, freeze, g0->stream)
+                       : evp::launch_predictor_zm(bm, g0->precision, g0->nx, g0->ny, g0->nz, freeze,
+                                                  g0->stream, g0->bc == EVP_WALLS, model, rk3);
+        });
+    }
+    return r;
+}
+
+// Sec. 3.3.1: three substeps per step.  Substep k: the stress update and the explicit momentum
+// terms (predictor), the stress divergence at B^k, then the projection with 2 alpha_k dt.  The
+// projection solves for p^k itself: the predictor leaves out -2 alpha_k dt grad p^{k-1} / rho, and
+// with the exact discrete Poisson solve p^{k-1} + psi^k is the potential of that velocity.
+int enqueue_rk3(evp_grid* const* gs, int count, double dt, int nsteps, unsigned flags)
+{
+    evp_grid* g0 = gs[0];
+    const bool freeze = (flags & EVP_FREEZE_VELOCITY) != 0;
+    for (int s = 0; s < nsteps; ++s) {
+        for (int k = 0; k < 3; ++k) {
+            Batch b{};
+            b.count = count;
+            b.rk[0] = kRkZeta[k];
+            b.rk[1] = kRkXi[k];
+            b.rk[2] = kRkAlpha[k];
+            for (int i = 0; i < count; ++i) {
+                b.d[i] = gs[i]->d;
+                b.dt[i] = dt;
+                b.state[i] = gs[i]->parity | (k == 0 ? evp::ST_EULER : 0);
+            }
+            int r = predictor_by_model(gs, b, freeze, true);
+            if (r) return r;
+            if (!freeze) {
+                r = timed(g0, EVP_K_STRESS_DIV, [&] {
+                    return evp::launch_stress_div(b, g0->precision, g0->nx, g0->ny, g0->nz,
+                                                  g0->bc == EVP_WALLS, g0->stream);
+                });
+                if (r) return r;
+                Batch bp = b;
+                for (int i = 0; i < count; ++i) bp.dt[i] = 2.0 * kRkAlpha[k] * dt;
+                if ((r = projection(g0, bp))) return r;
+            }
+            for (int i = 0; i < count; ++i) gs[i]->parity ^= 1;
+        }
+        for (int i = 0; i < count; ++i) {
+            gs[i]->have_hist = false;     // the scheme keeps no history across steps
+            gs[i]->nstep += 1;
+        }
+    }
+    return EVP_OK;
+}
+
 int enqueue_steps(evp_grid* const* gs, int count, double dt, int nsteps, unsigned flags)
 {
+    if (gs[0]->integrator == EVP_RK3) return enqueue_rk3(gs, count, dt, nsteps, flags);
     evp_grid* g0 = gs[0];
     const bool freeze = (flags & EVP_FREEZE_VELOCITY) != 0;
     const bool stop = (flags & EVP_STOP_AFTER_PREDICTOR) != 0;
@@ -281,26 +358,7 @@ int enqueue_steps(evp_grid* const* gs, int count, double dt, int nsteps, unsigne
             b.dt[i] = dt;
             b.state[i] = gs[i]->parity | (gs[i]->have_hist ? 0 : evp::ST_EULER);
         }
-        // the predictor is specialised per constitutive model: one launch per model present, so
-        // a grid's arithmetic is the same alone and in any batch
-        int r = EVP_OK;
-        for (int model = EVP_OLDROYD_B; model <= EVP_SARAMITO && !r; ++model) {
-            Batch bm{};
-            for (int i = 0; i < count; ++i)
-                if (gs[i]->h.model == model) {
-                    bm.d[bm.count] = b.d[i];
-                    bm.dt[bm.count] = b.dt[i];
-                    bm.state[bm.count] = b.state[i];
-                    bm.count++;
-                }
-            if (bm.count == 0) continue;
-            r = timed(g0, EVP_K_PREDICTOR, [&] {
-                return use_reference_predictor()
-                           ? evp::launch_predictor_ref(bm, g0->precision, g0->nx, g0->ny, g0->nz, freeze, g0->stream)
-                           : evp::launch_predictor_zm(bm, g0->precision, g0->nx, g0->ny, g0->nz, freeze,
-                                                      g0->stream, g0->bc == EVP_WALLS, model);
-            });
-        }
+        int r = predictor_by_model(gs, b, freeze, false);
         if (r) return r;
         if (stop && !freeze) {
             hipError_t e = evp::launch_copy_ustar(b, g0->nx, g0->ny, g0->nz, true, g0->stream);
@@ -500,6 +558,15 @@ int evp_project(evp_grid* g)
     return r;
 }
 
+int evp_set_integrator(evp_grid* g, int scheme)
+{
+    if (int r = check_grid(g)) return r;
+    if (scheme != EVP_AB2 && scheme != EVP_RK3) return fail(EVP_ERR_ARG, "scheme must be EVP_AB2 or EVP_RK3");
+    if (scheme != g->integrator) g->have_hist = false;    // the other scheme's history is void
+    g->integrator = scheme;
+    return EVP_OK;
+}
+
 int evp_step(evp_grid* g, double dt, int nsteps, unsigned flags)
 {
     if (int r = check_grid(g)) return r;
@@ -517,6 +584,10 @@ int evp_step_batch(evp_grid* const* grids, int count, double dt, int nsteps, uns
     if (flags & ~(EVP_FREEZE_VELOCITY | EVP_STOP_AFTER_PREDICTOR)) return fail(EVP_ERR_ARG, "unknown flag");
     const evp_grid* g0 = grids[0];
     if (!g0) return fail(EVP_ERR_ARG, "null grid in batch");
+    if (g0->integrator == EVP_RK3 && (flags & EVP_STOP_AFTER_PREDICTOR))
+        return fail(EVP_ERR_ARG, "EVP_STOP_AFTER_PREDICTOR applies to the AB2 step only");
+    if (g0->integrator == EVP_RK3 && use_reference_predictor())
+        return fail(EVP_ERR_ARG, "the per-cell reference predictor implements the AB2 step only");
     for (int i = 0; i < count; ++i) {
         const evp_grid* g = grids[i];
         if (!g) return fail(EVP_ERR_ARG, "null grid in batch");
@@ -525,6 +596,8 @@ int evp_step_batch(evp_grid* const* grids, int count, double dt, int nsteps, uns
         if (g->nx != g0->nx || g->ny != g0->ny || g->nz != g0->nz || g->bc != g0->bc ||
             g->precision != g0->precision || g->stream != g0->stream)
             return fail(EVP_ERR_SHAPE, "batch grids must share shape, boundary type, precision and stream");
+        if (g->integrator != g0->integrator)
+            return fail(EVP_ERR_SHAPE, "batch grids must share the time integrator");
         if (!g->have_rheo) return fail(EVP_ERR_STATE, "step before set_rheology");
         if (!g->have_fields) return fail(EVP_ERR_STATE, "step before write_fields");
     }

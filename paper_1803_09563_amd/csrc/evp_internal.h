@@ -40,8 +40,9 @@ struct Desc {
 struct Batch {
     const Desc* d[EVP_MAX_BATCH];
     double dt[EVP_MAX_BATCH];
-    int state[EVP_MAX_BATCH];    // bit 0: index of the current B buffer; bit 1: no AB2 history
+    int state[EVP_MAX_BATCH];    // bit 0: index of the current B buffer; bit 1: no history term
     int count;
+    double rk[3];                // Runge-Kutta substep: zeta, xi, alpha (Eq. RK); unused by AB2
 };
 
 constexpr int ST_PARITY = 1;
@@ -51,7 +52,9 @@ constexpr int ST_EULER = 2;
 hipError_t launch_predictor_ref(const Batch& b, int precision, int nx, int ny, int nz, bool freeze,
                                 hipStream_t s);
 hipError_t launch_predictor_zm(const Batch& b, int precision, int nx, int ny, int nz, bool freeze,
-                               hipStream_t s, bool walls, int model);
+                               hipStream_t s, bool walls, int model, bool rk3);
+hipError_t launch_stress_div(const Batch& b, int precision, int nx, int ny, int nz, bool walls,
+                             hipStream_t s);
 int predictor_chunk(int nx, int ny, int nz);
 hipError_t launch_div_fftx(const Batch& b, int nx, int ny, int nz, hipStream_t s);
 hipError_t launch_fft_strided(const Batch& b, int nx, int ny, int nz, int axis, bool inverse,

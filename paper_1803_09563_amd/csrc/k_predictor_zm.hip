@@ -91,7 +91,12 @@ __device__ __forceinline__ T weno_up(T f0, T f1, T f2, T f3, T f4, T f5, T f6, T
     return weno5u<T>(v1, v2, v3, v4, v5, eps2);
 }
 
-template <typename T, bool WALLS, int MODEL>
+// RK3: the substep of Sec. 3.3.1 instead of AB2.  B^k = B^{k-1} + dt (zeta RT^{k-1} + xi RT^{k-2});
+// the momentum part leaves out the stress divergence at the new level (added by k_stress_div once
+// B^k is complete) and the pressure gradient (the projection then yields p^k itself), and keeps
+// the advection term as the history: u~ = u + dt [-zeta A^{k-1} - xi A^{k-2}
+// + (2 alpha (mu_s lap u + f) + alpha div tau^{k-1}) / rho].
+template <typename T, bool WALLS, int MODEL, bool RK3>
 __global__ __launch_bounds__(NTH, 2) void k_pred_zm(Batch B, int freeze, int kc)
 {
     __shared__ Smem<T> S;
@@ -120,7 +125,9 @@ __global__ __launch_bounds__(NTH, 2) void k_pred_zm(Batch B, int freeze, int kc)
     T* __restrict__ RU = (T*)D.RU;
     const bool euler = (st & ST_EULER) != 0;
     const T dt = (T)B.dt[b];
-    const T c1 = euler ? (T)1 : (T)1.5, c2 = euler ? (T)0 : (T)-0.5;
+    // history weights: AB2 (3/2, -1/2; Euler start 1, 0) or the substep's (zeta, xi)
+    const T c1 = RK3 ? (T)B.rk[0] : (euler ? (T)1 : (T)1.5);
+    const T c2 = euler ? (T)0 : (RK3 ? (T)B.rk[1] : (T)-0.5);
     constexpr bool fene = MODEL == EVP_FENE_P, sara = MODEL == EVP_SARAMITO;
     const T G = (T)D.G, L2 = (T)D.L2, afene = (T)D.a_fene, il = (T)D.inv_lam, tyld = (T)D.tau_y;
     const T idx = (T)D.idx, idy = (T)D.idy, idz = (T)D.idz;
@@ -380,6 +387,9 @@ __global__ __launch_bounds__(NTH, 2) void k_pred_zm(Batch B, int freeze, int kc)
                         (((cc) == 0 || (cc) == 3 || (cc) == 5) ? S.ga[rb + (dj)][cb + (di)] : (T)0)) \
                         : G * S.B[cc][r + (dj)][c + (di)])
 #define TZ(s, zc, di, dj) S.Z[s][zc][rb + (dj)][cb + (di)]
+                // face terms; RK3 keeps the advection (history) apart from the rest (mx, my, mz)
+                const T cal = RK3 ? (T)B.rk[2] : (T)0;
+                T mx = (T)0, my = (T)0, mz = (T)0;
                 // x-face (i+1/2, j, k)
                 T rux;
                 {
@@ -395,7 +405,8 @@ __global__ __launch_bounds__(NTH, 2) void k_pred_zm(Batch B, int freeze, int kc)
                     const T dtau = (TK(0, 1, 0) - TK(0, 0, 0)) * idx
                                  + qt * (TK(1, 0, 1) + TK(1, 1, 1) - TK(1, 0, -1) - TK(1, 1, -1)) * idy
                                  + qt * (TZ(sp, 0, 0, 0) + TZ(sp, 0, 1, 0) - TZ(sm, 0, 0, 0) - TZ(sm, 0, 1, 0)) * idz;
-                    rux = -adv + (ms * lap + dtau + fx) * irho;
+                    if constexpr (RK3) { rux = adv; mx = (T)2 * cal * (ms * lap + fx) + cal * dtau; }
+                    else rux = -adv + (ms * lap + dtau + fx) * irho;
                 }
                 // y-face (i, j+1/2, k)
                 T ruy = (T)0;
@@ -412,7 +423,8 @@ __global__ __launch_bounds__(NTH, 2) void k_pred_zm(Batch B, int freeze, int kc)
                     const T dtau = qt * (TK(1, 1, 0) + TK(1, 1, 1) - TK(1, -1, 0) - TK(1, -1, 1)) * idx
                                  + (TK(3, 0, 1) - TK(3, 0, 0)) * idy
                                  + qt * (TZ(sp, 1, 0, 0) + TZ(sp, 1, 0, 1) - TZ(sm, 1, 0, 0) - TZ(sm, 1, 0, 1)) * idz;
-                    ruy = -adv + (ms * lap + dtau) * irho;
+                    if constexpr (RK3) { ruy = adv; my = (T)2 * cal * (ms * lap) + cal * dtau; }
+                    else ruy = -adv + (ms * lap + dtau) * irho;
                 }
                 // z-face (i, j, k+1/2)
                 T ruz;
@@ -429,14 +441,21 @@ __global__ __launch_bounds__(NTH, 2) void k_pred_zm(Batch B, int freeze, int kc)
                     const T dtau = qt * (TZ(s0, 0, 1, 0) + TZ(sp, 0, 1, 0) - TZ(s0, 0, -1, 0) - TZ(sp, 0, -1, 0)) * idx
                                  + qt * (TZ(s0, 1, 0, 1) + TZ(sp, 1, 0, 1) - TZ(s0, 1, 0, -1) - TZ(sp, 1, 0, -1)) * idy
                                  + (TZ(sp, 2, 0, 0) - TZ(s0, 2, 0, 0)) * idz;
-                    ruz = -adv + (ms * lap + dtau) * irho;
+                    if constexpr (RK3) { ruz = adv; mz = (T)2 * cal * (ms * lap) + cal * dtau; }
+                    else ruz = -adv + (ms * lap + dtau) * irho;
                 }
 #undef TK
 #undef TZ
                 const T ox = euler ? (T)0 : RU[q], oy = euler ? (T)0 : RU[ps + q], oz = euler ? (T)0 : RU[2 * ps + q];
-                D.us[q] = gu[q] + (double)(dt * (c1 * rux + c2 * ox));
-                D.vs[q] = vwall ? 0.0 : gv[q] + (double)(dt * (c1 * ruy + c2 * oy));
-                D.ws[q] = gw[q] + (double)(dt * (c1 * ruz + c2 * oz));
+                if constexpr (RK3) {
+                    D.us[q] = gu[q] + (double)(dt * (mx * irho - c1 * rux - c2 * ox));
+                    D.vs[q] = vwall ? 0.0 : gv[q] + (double)(dt * (my * irho - c1 * ruy - c2 * oy));
+                    D.ws[q] = gw[q] + (double)(dt * (mz * irho - c1 * ruz - c2 * oz));
+                } else {
+                    D.us[q] = gu[q] + (double)(dt * (c1 * rux + c2 * ox));
+                    D.vs[q] = vwall ? 0.0 : gv[q] + (double)(dt * (c1 * ruy + c2 * oy));
+                    D.ws[q] = gw[q] + (double)(dt * (c1 * ruz + c2 * oz));
+                }
                 RU[q] = rux; RU[ps + q] = ruy; RU[2 * ps + q] = ruz;
             }
 #undef VU
@@ -468,13 +487,17 @@ int predictor_chunk(int nx, int ny, int nz)
 }
 
 hipError_t launch_predictor_zm(const Batch& b, int precision, int nx, int ny, int nz, bool freeze,
-                               hipStream_t s, bool walls, int model)
+                               hipStream_t s, bool walls, int model, bool rk3)
 {
     const int kc = predictor_chunk(nx, ny, nz);
     const int nblk = ((nx + TX - 1) / TX) * ((ny + TY - 1) / TY) * ((nz + kc - 1) / kc);
     dim3 grid(nblk, b.count);
     const int fz = freeze ? 1 : 0;
-#define EVP_LAUNCH(TT, WW, MM) hipLaunchKernelGGL((k_pred_zm<TT, WW, MM>), grid, dim3(NTH), 0, s, b, fz, kc)
+#define EVP_LAUNCH(TT, WW, MM)                                                                     \
+    do {                                                                                           \
+        if (rk3) hipLaunchKernelGGL((k_pred_zm<TT, WW, MM, true>), grid, dim3(NTH), 0, s, b, fz, kc); \
+        else hipLaunchKernelGGL((k_pred_zm<TT, WW, MM, false>), grid, dim3(NTH), 0, s, b, fz, kc); \
+    } while (0)
 #define EVP_BY_MODEL(TT, WW)                                                                       \
     switch (model) {                                                                               \
     case EVP_FENE_P: EVP_LAUNCH(TT, WW, EVP_FENE_P); break;                                       \
