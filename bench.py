@@ -28,6 +28,8 @@ PRED_BYTES = {"fp64": 24 + 6 * 8 * 4 + 3 * 8 * 2 + 24, "mixed": 24 + 6 * 4 * 4 +
 # whole step: predictor + Poisson RHS/x-FFT (32) + 3 spectrum passes (48) + inverse x-FFT and
 # correction (72)
 STEP_BYTES = {k: v + 32 + 48 + 72 for k, v in PRED_BYTES.items()}
+# RK3 stress divergence: read B^k (6), read and write u* (3 FP64 each way)
+STRESS_DIV_BYTES = {"fp64": 6 * 8 + 48, "mixed": 6 * 4 + 48}
 
 
 TRAFFIC_FILE = os.path.join(HERE, "profiles", "predictor_kolmogorov128_hbm_traffic.txt")
@@ -61,6 +63,7 @@ def _args():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=0, help="oracle steps (0 = size to ~15 s)")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-rk3", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=500)
     ap.add_argument("--quiet", action="store_true")
     return ap.parse_args()
@@ -71,7 +74,7 @@ def _log(msg, quiet=False):
         print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def run_gpu(wl, precision, steps, warmup, quiet):
+def run_gpu(wl, precision, steps, warmup, quiet, integrator="ab2"):
     import torch
     import paper_1803_09563_amd as evp
     from paper_1803_09563_amd import inputs
@@ -80,12 +83,13 @@ def run_gpu(wl, precision, steps, warmup, quiet):
     G = evp.Grid(wl.nx, wl.ny, wl.nz, wl.lx, wl.ly, wl.lz, walls=wl.walls, precision=prec)
     G.set_rheology(**wl.rheology())
     G.set_forcing(*wl.force)
+    G.set_integrator(integrator)
     u, v, w, B = [torch.from_numpy(a).cuda() for a in inputs.initial_fields(wl)]
     G.write_fields(u, v, w, B)
     G.project()
     G.step(wl.dt, warmup)
     torch.cuda.synchronize()
-    _log(f"{precision}: warmup {warmup} steps done", quiet)
+    _log(f"{precision} {integrator}: warmup {warmup} steps done", quiet)
 
     stream = G.stream
     t0 = torch.cuda.Event(enable_timing=True)
@@ -98,7 +102,7 @@ def run_gpu(wl, precision, steps, warmup, quiet):
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
     ms = t0.elapsed_time(t1)
-    _log(f"{precision}: timed {steps} steps in {ms:.2f} ms (wall {wall * 1e3:.2f} ms)", quiet)
+    _log(f"{precision} {integrator}: timed {steps} steps in {ms:.2f} ms (wall {wall * 1e3:.2f} ms)", quiet)
 
     # per-kernel HIP-event timing on the library's stream, over a second timed region
     G.profile(True)
@@ -182,7 +186,7 @@ def main():
     kernels = {}
     for prec, r in res.items():
         kernels[prec] = {k: round(v["ms"] / max(v["launches"], 1) * 1e3, 2)
-                         for k, v in r["prof"].items()}
+                         for k, v in r["prof"].items() if v["launches"]}
     out = {
         "metric": "cell-steps/s (stress+FFT projection) FP64 vs mixed; p50/p99 sweep-solve latency",
         "value": value,
@@ -216,6 +220,18 @@ def main():
                         "predictor_avg_us": mpred * 1e3,
                         "predictor_hbm_frac": PRED_BYTES["mixed"] * wl.ncell / (mpred * 1e-3) / 1e9 / HBM_PEAK_GBS,
                         "step_hbm_frac": STEP_BYTES["mixed"] * mv / 1e9 / HBM_PEAK_GBS}
+    if not a.no_rk3:
+        # the paper's other integrator (Sec. 3.3.1): three substeps per step, same workload and dt
+        rk = run_gpu(wl, "fp64", max(a.steps // 3, 1), a.warmup, a.quiet, integrator="rk3")
+        n_rk = max(a.steps // 3, 1)
+        sd = rk["prof"]["stress_div"]
+        sd_ms = sd["ms"] / max(sd["launches"], 1)
+        out["rk3"] = {"value": wl.ncell * n_rk / (rk["ms"] * 1e-3), "unit": "cell-steps/s",
+                      "steps": n_rk, "ms_per_step": rk["ms"] / n_rk, "precision": "fp64",
+                      "kernel_avg_us": {k: round(v["ms"] / max(v["launches"], 1) * 1e3, 2)
+                                        for k, v in rk["prof"].items() if v["launches"]},
+                      "stress_div_hbm_frac": STRESS_DIV_BYTES["fp64"] * wl.ncell / (sd_ms * 1e-3)
+                      / 1e9 / HBM_PEAK_GBS}
     if not a.no_serving:
         out["serving"] = serving(a.serving_requests, a.quiet)
     if not a.no_cpu_baseline:

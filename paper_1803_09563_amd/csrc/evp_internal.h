@@ -45,6 +45,13 @@ struct Batch {
     double rk[3];                // Runge-Kutta substep: zeta, xi, alpha (Eq. RK); unused by AB2
 };
 
+// Pointers into the workspace as global-memory (address space 1) pointers: accesses through them
+// compile to global_* instructions, which count only against the vector-memory counter, so a
+// wait for LDS results does not also wait for global loads in flight (flat instructions, which
+// generic pointers produce, count against both).
+#define EVP_GLOBAL __attribute__((address_space(1)))
+template <typename T> using gptr = EVP_GLOBAL T*;
+
 constexpr int ST_PARITY = 1;
 constexpr int ST_EULER = 2;
 

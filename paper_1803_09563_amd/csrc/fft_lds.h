@@ -20,6 +20,22 @@ __device__ __forceinline__ double2 cscale(double2 a, double s) { return make_dou
 // multiply by -i
 __device__ __forceinline__ double2 cmi(double2 a) { return make_double2(a.y, -a.x); }
 
+// Complex values in global memory, accessed through address-space-1 pointers as native two-lane
+// vectors (the HIP vector class has no assignment for address-space-qualified objects).
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ double2 gload2(gptr<const double2> p)
+{
+    const dvec2 t = *(gptr<const dvec2>)p;
+    return make_double2(t.x, t.y);
+}
+__device__ __forceinline__ void gstore2(gptr<double2> p, double2 v)
+{
+    dvec2 t;
+    t.x = v.x;
+    t.y = v.y;
+    *(gptr<dvec2>)p = t;
+}
+
 struct FftPlan {
     int n, nst;
     int r[10];

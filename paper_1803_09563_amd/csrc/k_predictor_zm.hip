@@ -119,10 +119,10 @@ __global__ __launch_bounds__(NTH, 2) void k_pred_zm(Batch B, int freeze, int kc)
     const int oij = jc * nx + ic;
 
     const int st = B.state[b];
-    const T* __restrict__ Bin = (const T*)D.Bt[st & 1];
-    T* __restrict__ Bout = (T*)D.Bt[(st & 1) ^ 1];
-    T* __restrict__ RT = (T*)D.RT;
-    T* __restrict__ RU = (T*)D.RU;
+    const gptr<const T> __restrict__ Bin = (gptr<const T>)D.Bt[st & 1];
+    const gptr<T> __restrict__ Bout = (gptr<T>)D.Bt[(st & 1) ^ 1];
+    const gptr<T> __restrict__ RT = (gptr<T>)D.RT;
+    const gptr<T> __restrict__ RU = (gptr<T>)D.RU;
     const bool euler = (st & ST_EULER) != 0;
     const T dt = (T)B.dt[b];
     // history weights: AB2 (3/2, -1/2; Euler start 1, 0) or the substep's (zeta, xi)
@@ -132,9 +132,12 @@ __global__ __launch_bounds__(NTH, 2) void k_pred_zm(Batch B, int freeze, int kc)
     const T G = (T)D.G, L2 = (T)D.L2, afene = (T)D.a_fene, il = (T)D.inv_lam, tyld = (T)D.tau_y;
     const T idx = (T)D.idx, idy = (T)D.idy, idz = (T)D.idz;
     const T e2x = (T)(1e-6 * D.dx * D.dx), e2y = (T)(1e-6 * D.dy * D.dy), e2z = (T)(1e-6 * D.dz * D.dz);
-    const double* __restrict__ gu = D.u;
-    const double* __restrict__ gv = D.v;
-    const double* __restrict__ gw = D.w;
+    const gptr<const double> __restrict__ gu = (gptr<const double>)D.u;
+    const gptr<const double> __restrict__ gv = (gptr<const double>)D.v;
+    const gptr<const double> __restrict__ gw = (gptr<const double>)D.w;
+    const gptr<double> __restrict__ gus = (gptr<double>)D.us;
+    const gptr<double> __restrict__ gvs = (gptr<double>)D.vs;
+    const gptr<double> __restrict__ gws = (gptr<double>)D.ws;
 
     // ---- staging descriptors, computed once: the per-plane offsets do not depend on k ----
     // Interior slots (the block's own cells) are filled from the thread's register window; only
@@ -193,7 +196,7 @@ __global__ __launch_bounds__(NTH, 2) void k_pred_zm(Batch B, int freeze, int kc)
     const Src os = bsrc(modp(i, nx), j);           // used only when the cell is outside the domain
     const VSrc ov = vsrc(modp(i, nx), j);
 
-    auto bload = [&](const T* p, int cc, const Src& q) {
+    auto bload = [&](gptr<const T> p, int cc, const Src& q) {
         T x = p[cc * ps + q.a];
         if (WALLS) x = q.wa * x + q.wb * p[cc * ps + q.b];
         return x;
@@ -221,7 +224,7 @@ __global__ __launch_bounds__(NTH, 2) void k_pred_zm(Batch B, int freeze, int kc)
     T* const sB = &S.B[0][0][0];
     // B - I of plane kk with the cross halo into S.B (own value: the window entry of plane kk)
     auto load_bplane = [&](int kk, const T* own) {
-        const T* bk = Bin + kk * sxy;
+        const gptr<const T> bk = Bin + kk * sxy;
         T hvv[6], ovv[6];
 #pragma unroll
         for (int cc = 0; cc < 6; ++cc) {
@@ -238,8 +241,8 @@ __global__ __launch_bounds__(NTH, 2) void k_pred_zm(Batch B, int freeze, int kc)
     // ring slot sl <- tau_xz, tau_yz, tau_zz and u, v, w of plane kz (own B - I values: ownz);
     // if ownk != nullptr also the stress factors of plane k (own values: ownk)
     auto load_box = [&](int kz, const T* ownz, int sl, int kg, const T* ownk) {
-        const T* bz = Bin + kz * sxy;
-        const T* bg = Bin + kg * sxy;
+        const gptr<const T> bz = Bin + kz * sxy;
+        const gptr<const T> bg = Bin + kg * sxy;
         const int kv = kz * sxy;
         // halo slot
         T hz[3], hvel[3], hgf = G, hga = (T)0;
@@ -287,7 +290,7 @@ __global__ __launch_bounds__(NTH, 2) void k_pred_zm(Batch B, int freeze, int kc)
     T win[7][6];
 #pragma unroll
     for (int m = 0; m < 6; ++m) {
-        const T* p = Bin + modp(k0 - 3 + m, nz) * sxy + oij;
+        const gptr<const T> p = Bin + modp(k0 - 3 + m, nz) * sxy + oij;
 #pragma unroll
         for (int cc = 0; cc < 6; ++cc) win[m][cc] = p[cc * ps];
     }
@@ -302,7 +305,7 @@ __global__ __launch_bounds__(NTH, 2) void k_pred_zm(Batch B, int freeze, int kc)
     for (int k = k0; k < k1; ++k) {
         const int kp = modp(k + 1, nz);
         {
-            const T* p = Bin + modp(k + 3, nz) * sxy + oij;
+            const gptr<const T> p = Bin + modp(k + 3, nz) * sxy + oij;
 #pragma unroll
             for (int cc = 0; cc < 6; ++cc) win[6][cc] = p[cc * ps];
         }
@@ -379,7 +382,7 @@ __global__ __launch_bounds__(NTH, 2) void k_pred_zm(Batch B, int freeze, int kc)
 
             __asm__ volatile("" ::: "memory");
             if (freeze) {
-                D.us[q] = gu[q]; D.vs[q] = gv[q]; D.ws[q] = gw[q];
+                gus[q] = gu[q]; gvs[q] = gv[q]; gws[q] = gw[q];
                 RU[q] = (T)0; RU[ps + q] = (T)0; RU[2 * ps + q] = (T)0;
             } else {
                 // stresses of plane k from B - I and the staged factors
@@ -448,13 +451,13 @@ __global__ __launch_bounds__(NTH, 2) void k_pred_zm(Batch B, int freeze, int kc)
 #undef TZ
                 const T ox = euler ? (T)0 : RU[q], oy = euler ? (T)0 : RU[ps + q], oz = euler ? (T)0 : RU[2 * ps + q];
                 if constexpr (RK3) {
-                    D.us[q] = gu[q] + (double)(dt * (mx * irho - c1 * rux - c2 * ox));
-                    D.vs[q] = vwall ? 0.0 : gv[q] + (double)(dt * (my * irho - c1 * ruy - c2 * oy));
-                    D.ws[q] = gw[q] + (double)(dt * (mz * irho - c1 * ruz - c2 * oz));
+                    gus[q] = gu[q] + (double)(dt * (mx * irho - c1 * rux - c2 * ox));
+                    gvs[q] = vwall ? 0.0 : gv[q] + (double)(dt * (my * irho - c1 * ruy - c2 * oy));
+                    gws[q] = gw[q] + (double)(dt * (mz * irho - c1 * ruz - c2 * oz));
                 } else {
-                    D.us[q] = gu[q] + (double)(dt * (c1 * rux + c2 * ox));
-                    D.vs[q] = vwall ? 0.0 : gv[q] + (double)(dt * (c1 * ruy + c2 * oy));
-                    D.ws[q] = gw[q] + (double)(dt * (c1 * ruz + c2 * oz));
+                    gus[q] = gu[q] + (double)(dt * (c1 * rux + c2 * ox));
+                    gvs[q] = vwall ? 0.0 : gv[q] + (double)(dt * (c1 * ruy + c2 * oy));
+                    gws[q] = gw[q] + (double)(dt * (c1 * ruz + c2 * oz));
                 }
                 RU[q] = rux; RU[ps + q] = ruy; RU[2 * ps + q] = ruz;
             }

@@ -24,7 +24,7 @@ __device__ __forceinline__ int wrapi(int i, int n) { return i < 0 ? i + n : (i >
 // c = e % TK).  The column is the same for every m of a thread, so its bounds check is hoisted;
 // loads are issued in groups of up to 16 before their LDS stores.
 template <int N, bool CONJ>
-__device__ __forceinline__ void tile_in(double2* buf, const double2* __restrict__ src, long long es,
+__device__ __forceinline__ void tile_in(double2* buf, gptr<const double2> __restrict__ src, long long es,
                                         bool colok, int tid)
 {
     constexpr int TOT = N * TK, M = (TOT + NT - 1) / NT, G = M < 16 ? M : 16;
@@ -35,7 +35,8 @@ __device__ __forceinline__ void tile_in(double2* buf, const double2* __restrict_
 #pragma unroll
         for (int m = 0; m < G; ++m) {
             const int n = n0 + (g0 + m) * (NT / TK);
-            v[m] = (colok && n < N) ? src[n * es + c] : make_double2(0.0, 0.0);
+            v[m] = make_double2(0.0, 0.0);
+            if (colok && n < N) v[m] = gload2(src + n * es + c);
         }
 #pragma unroll
         for (int m = 0; m < G; ++m) {
@@ -46,7 +47,7 @@ __device__ __forceinline__ void tile_in(double2* buf, const double2* __restrict_
 }
 
 template <int N, bool CONJ>
-__device__ __forceinline__ void tile_out(const double2* buf, double2* __restrict__ dst, long long es,
+__device__ __forceinline__ void tile_out(const double2* buf, gptr<double2> __restrict__ dst, long long es,
                                          bool colok, int tid)
 {
     constexpr int TOT = N * TK, M = (TOT + NT - 1) / NT;
@@ -57,7 +58,7 @@ __device__ __forceinline__ void tile_out(const double2* buf, double2* __restrict
         const int n = n0 + m * (NT / TK);
         if (n < N) {
             const double2 x = buf[n * TK + c];
-            dst[n * es + c] = CONJ ? cconj(x) : x;
+            gstore2(dst + n * es + c, CONJ ? cconj(x) : x);
         }
     }
 }
@@ -76,7 +77,11 @@ __global__ __launch_bounds__(NT) void k_div_fftx(Batch B)
     const Desc& D = *B.d[blockIdx.y];
     const double sc = D.rho / B.dt[blockIdx.y];
     const int tid = threadIdx.x;
-    for (int n = tid; n < N; n += NT) tw[n] = D.twx[n];
+    for (int n = tid; n < N; n += NT) tw[n] = gload2((gptr<const double2>)D.twx + n);
+    const gptr<const double> us = (gptr<const double>)D.us;
+    const gptr<const double> vs = (gptr<const double>)D.vs;
+    const gptr<const double> ws = (gptr<const double>)D.ws;
+    const gptr<double2> spec = (gptr<double2>)D.spec;
     const int ny = D.ny, nz = D.nz;
     const int nlines = ny * nz;
     const int npairs = (nlines + 1) >> 1;
@@ -105,12 +110,12 @@ __global__ __launch_bounds__(NT) void k_div_fftx(Batch B)
                 l = ok ? l : 0;
                 const int k = l / ny, j = l - k * ny;
                 const long long q = (long long)l * N + i;
-                ld[m][h][0] = D.us[q];
-                ld[m][h][1] = D.us[q - i + wrapi(i - 1, N)];
-                ld[m][h][2] = D.vs[q];
-                ld[m][h][3] = (j > 0) ? D.vs[q - N] : D.vs[q + (long long)(ny - 1) * N];
-                ld[m][h][4] = D.ws[q];
-                ld[m][h][5] = (k > 0) ? D.ws[q - sxy] : D.ws[q + (long long)(nz - 1) * sxy];
+                ld[m][h][0] = us[q];
+                ld[m][h][1] = us[q - i + wrapi(i - 1, N)];
+                ld[m][h][2] = vs[q];
+                ld[m][h][3] = (j > 0) ? vs[q - N] : vs[q + (long long)(ny - 1) * N];
+                ld[m][h][4] = ws[q];
+                ld[m][h][5] = (k > 0) ? ws[q - sxy] : ws[q + (long long)(nz - 1) * sxy];
                 ld[m][h][6] = (ok ? 1.0 : 0.0) * ((j == 0 && walls) ? 0.0 : 1.0);   // flags
                 if (!ok) ld[m][h][6] = -1.0;
             }
@@ -141,9 +146,9 @@ __global__ __launch_bounds__(NT) void k_div_fftx(Batch B)
         const double2 Zc = cconj(buf[l2 * N + (k == 0 ? 0 : N - k)]);
         const double2 s = cadd(Z, Zc), d = csub(Z, Zc);
         const int la = 2 * pair;
-        D.spec[(long long)la * nh + k] = make_double2(0.5 * s.x, 0.5 * s.y);
+        gstore2(spec + (long long)la * nh + k, make_double2(0.5 * s.x, 0.5 * s.y));
         if (la + 1 < nlines)
-            D.spec[(long long)(la + 1) * nh + k] = make_double2(0.5 * d.y, -0.5 * d.x);
+            gstore2(spec + (long long)(la + 1) * nh + k, make_double2(0.5 * d.y, -0.5 * d.x));
     }
 }
 
@@ -161,8 +166,9 @@ __global__ __launch_bounds__(NT) void k_fft_strided(Batch B, int axis)
     __shared__ double2 tw[N];
     const Desc& D = *B.d[blockIdx.y];
     const int tid = threadIdx.x;
-    const double2* twg = axis == 1 ? D.twy : D.twz;
-    for (int n = tid; n < N; n += NT) tw[n] = twg[n];
+    const gptr<const double2> twg = (gptr<const double2>)(axis == 1 ? D.twy : D.twz);
+    const gptr<double2> spec = (gptr<double2>)D.spec;
+    for (int n = tid; n < N; n += NT) tw[n] = gload2(twg + n);
     const int nh = D.nh, ny = D.ny;
     const int ntk = (nh + TK - 1) / TK;
     const int tile = blockIdx.x % ntk, other = blockIdx.x / ntk;
@@ -171,11 +177,11 @@ __global__ __launch_bounds__(NT) void k_fft_strided(Batch B, int axis)
     if (axis == 1) { base = (long long)other * ny * nh + kx0; es = nh; }
     else { base = (long long)other * nh + kx0; es = (long long)nh * ny; }
     const bool colok = kx0 + tid % TK < nh;
-    tile_in<N, INV>(buf, D.spec + base, es, colok, tid);
+    tile_in<N, INV>(buf, spec + base, es, colok, tid);
     __syncthreads();
     const int c = tid % TK, t = tid / TK;
     fft_stages<N, T, 0, 1>(buf + c, TK, t, t < T, tw);
-    tile_out<N, INV>(buf, D.spec + base, es, colok, tid);
+    tile_out<N, INV>(buf, spec + base, es, colok, tid);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -189,25 +195,28 @@ __global__ __launch_bounds__(NT) void k_solve_periodic(Batch B)
     __shared__ double2 tw[N];
     const Desc& D = *B.d[blockIdx.y];
     const int tid = threadIdx.x;
-    for (int n = tid; n < N; n += NT) tw[n] = D.twz[n];
+    for (int n = tid; n < N; n += NT) tw[n] = gload2((gptr<const double2>)D.twz + n);
+    const gptr<double2> spec = (gptr<double2>)D.spec;
+    const gptr<const double> eigx = (gptr<const double>)D.eigx;
+    const gptr<const double> eigz = (gptr<const double>)D.eigz;
     const int nh = D.nh, ny = D.ny;
     const int ntk = (nh + TK - 1) / TK;
     const int tile = blockIdx.x % ntk, ky = blockIdx.x / ntk;
     const int kx0 = tile * TK;
     const long long base = (long long)ky * nh + kx0, es = (long long)nh * ny;
     const bool colok = kx0 + tid % TK < nh;
-    tile_in<N, false>(buf, D.spec + base, es, colok, tid);
+    tile_in<N, false>(buf, spec + base, es, colok, tid);
     __syncthreads();
     const int c = tid % TK, t = tid / TK;
     fft_stages<N, T, 0, 1>(buf + c, TK, t, t < T, tw);
     const double scale = 1.0 / ((double)D.nx * ny * N);
-    const double ey = D.eigy[ky];
+    const double ey = ((gptr<const double>)D.eigy)[ky];
     for (int e = tid; e < N * TK; e += NT) {
         const int kz = e / TK, cc = e - kz * TK;
         const int kx = kx0 + cc;
         double2 x = buf[e];
         if (kx < nh) {
-            const double den = D.eigx[kx] + ey + D.eigz[kz];
+            const double den = eigx[kx] + ey + eigz[kz];
             const double f = (kx == 0 && ky == 0 && kz == 0) ? 0.0 : scale / den;
             x = cscale(x, f);
         }
@@ -215,7 +224,7 @@ __global__ __launch_bounds__(NT) void k_solve_periodic(Batch B)
     }
     __syncthreads();
     fft_stages<N, T, 0, 1>(buf + c, TK, t, t < T, tw);
-    tile_out<N, true>(buf, D.spec + base, es, colok, tid);
+    tile_out<N, true>(buf, spec + base, es, colok, tid);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -232,8 +241,8 @@ __global__ __launch_bounds__(TH_NT) void k_thomas(Batch B)
     if (col >= nh * nz) return;
     const int kz = col / nh, kx = col - kz * nh;
     const int kzs = kz <= nz - kz ? kz : nz - kz;
-    const double* __restrict__ piv = D.piv + (long long)kzs * ny * nh + kx;
-    double2* __restrict__ s = D.spec + (long long)kz * ny * nh + kx;
+    const gptr<const double> __restrict__ piv = (gptr<const double>)D.piv + (long long)kzs * ny * nh + kx;
+    const gptr<double2> __restrict__ s = (gptr<double2>)D.spec + (long long)kz * ny * nh + kx;
     const double a = D.idy * D.idy;                  // sub- and super-diagonal 1/dy^2
     const double scale = 1.0 / ((double)D.nx * nz);  // inverse x and z transforms
     // forward sweep d'_j = (r_j - a d'_{j-1}) / (b_j - a c'_{j-1}); the loads of the next block
@@ -245,7 +254,7 @@ __global__ __launch_bounds__(TH_NT) void k_thomas(Batch B)
 #pragma unroll
         for (int m = 0; m < TH_P; ++m) {
             const int jj = min(j0 + m, ny - 1);
-            rr[m] = s[(long long)jj * nh];
+            rr[m] = gload2(s + (long long)jj * nh);
             ii[m] = piv[(long long)jj * nh];
         }
     };
@@ -256,7 +265,7 @@ __global__ __launch_bounds__(TH_NT) void k_thomas(Batch B)
         for (int m = 0; m < TH_P; ++m) {
             if (j0 + m < ny) {
                 dp = make_double2((scale * r[m].x - a * dp.x) * iv[m], (scale * r[m].y - a * dp.y) * iv[m]);
-                s[(long long)(j0 + m) * nh] = dp;
+                gstore2(s + (long long)(j0 + m) * nh, dp);
             }
         }
 #pragma unroll
@@ -268,7 +277,7 @@ __global__ __launch_bounds__(TH_NT) void k_thomas(Batch B)
 #pragma unroll
         for (int m = 0; m < TH_P; ++m) {
             const int jj = max(j1 - m, 0);
-            dd[m] = s[(long long)jj * nh];
+            dd[m] = gload2(s + (long long)jj * nh);
             cc[m] = a * piv[(long long)jj * nh];
         }
     };
@@ -279,7 +288,7 @@ __global__ __launch_bounds__(TH_NT) void k_thomas(Batch B)
         for (int m = 0; m < TH_P; ++m) {
             if (j1 - m >= 0) {
                 x = make_double2(r[m].x - iv[m] * x.x, r[m].y - iv[m] * x.y);
-                s[(long long)(j1 - m) * nh] = x;
+                gstore2(s + (long long)(j1 - m) * nh, x);
             }
         }
 #pragma unroll
@@ -288,11 +297,11 @@ __global__ __launch_bounds__(TH_NT) void k_thomas(Batch B)
     if (kx == 0 && kz == 0) {
         // gauge: zero volume mean of p is zero mean of the (0,0) mode over y
         double sum = 0.0;
-        for (int j = 0; j < ny; ++j) sum += s[(long long)j * nh].x;
+        for (int j = 0; j < ny; ++j) sum += gload2(s + (long long)j * nh).x;
         const double m = sum / ny;
         for (int j = 0; j < ny; ++j) {
-            double2 v = s[(long long)j * nh];
-            s[(long long)j * nh] = make_double2(v.x - m, v.y);
+            const double2 v = gload2(s + (long long)j * nh);
+            gstore2(s + (long long)j * nh, make_double2(v.x - m, v.y));
         }
     }
 }
@@ -309,7 +318,9 @@ __global__ __launch_bounds__(NT) void k_ifftx(Batch B)
     __shared__ double2 tw[N];
     const Desc& D = *B.d[blockIdx.y];
     const int tid = threadIdx.x;
-    for (int n = tid; n < N; n += NT) tw[n] = D.twx[n];
+    for (int n = tid; n < N; n += NT) tw[n] = gload2((gptr<const double2>)D.twx + n);
+    const gptr<const double2> spec = (gptr<const double2>)D.spec;
+    const gptr<double> p = (gptr<double>)D.p;
     const int nlines = D.ny * D.nz;
     const int npairs = (nlines + 1) >> 1;
     const int pair0 = blockIdx.x * LP;
@@ -329,8 +340,8 @@ __global__ __launch_bounds__(NT) void k_ifftx(Batch B)
             const int la = pair < npairs ? 2 * pair : 0;
             const int lb = (pair < npairs && la + 1 < nlines) ? la + 1 : la;
             const int k = n <= N / 2 ? n : N - n;
-            av[m] = D.spec[(long long)la * nh + k];
-            bv[m] = D.spec[(long long)lb * nh + k];
+            av[m] = gload2(spec + (long long)la * nh + k);
+            bv[m] = gload2(spec + (long long)lb * nh + k);
         }
 #pragma unroll
         for (int m = 0; m < G; ++m) {
@@ -357,8 +368,8 @@ __global__ __launch_bounds__(NT) void k_ifftx(Batch B)
         if (pair >= npairs) continue;
         const double2 z = cconj(buf[e]);
         const int la = 2 * pair;
-        D.p[(long long)la * N + n] = z.x;
-        if (la + 1 < nlines) D.p[(long long)(la + 1) * N + n] = z.y;
+        p[(long long)la * N + n] = z.x;
+        if (la + 1 < nlines) p[(long long)(la + 1) * N + n] = z.y;
     }
 }
 
@@ -375,16 +386,20 @@ __global__ __launch_bounds__(256) void k_correct(Batch B)
     const long long r = q / nx;
     const int j = (int)(r % ny), k = (int)(r / ny);
     const double c = B.dt[blockIdx.y] * D.inv_rho;
-    const double p0 = D.p[q];
-    const double px = D.p[q - i + (i + 1 == nx ? 0 : i + 1)];
+    const gptr<const double> p = (gptr<const double>)D.p;
+    const gptr<const double> us = (gptr<const double>)D.us, vs = (gptr<const double>)D.vs,
+                             ws = (gptr<const double>)D.ws;
+    const gptr<double> u = (gptr<double>)D.u, v = (gptr<double>)D.v, w = (gptr<double>)D.w;
+    const double p0 = p[q];
+    const double px = p[q - i + (i + 1 == nx ? 0 : i + 1)];
     const long long sxy = (long long)nx * ny;
-    const double pz = D.p[k + 1 == nz ? q - (long long)(nz - 1) * sxy : q + sxy];
-    D.u[q] = D.us[q] - c * (px - p0) * D.idx;
-    D.w[q] = D.ws[q] - c * (pz - p0) * D.idz;
+    const double pz = p[k + 1 == nz ? q - (long long)(nz - 1) * sxy : q + sxy];
+    u[q] = us[q] - c * (px - p0) * D.idx;
+    w[q] = ws[q] - c * (pz - p0) * D.idz;
     if (j + 1 == ny) {
-        D.v[q] = D.walls ? 0.0 : D.vs[q] - c * (D.p[q - (long long)(ny - 1) * nx] - p0) * D.idy;
+        v[q] = D.walls ? 0.0 : vs[q] - c * (p[q - (long long)(ny - 1) * nx] - p0) * D.idy;
     } else {
-        D.v[q] = D.vs[q] - c * (D.p[q + nx] - p0) * D.idy;
+        v[q] = vs[q] - c * (p[q + nx] - p0) * D.idy;
     }
 }
 
@@ -393,8 +408,10 @@ __global__ __launch_bounds__(256) void k_copy_ustar(Batch B, int to_u)
     const Desc& D = *B.d[blockIdx.y];
     const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
     if (q >= D.ncell) return;
-    if (to_u) { D.u[q] = D.us[q]; D.v[q] = D.vs[q]; D.w[q] = D.ws[q]; }
-    else { D.us[q] = D.u[q]; D.vs[q] = D.v[q]; D.ws[q] = D.w[q]; }
+    const gptr<double> u = (gptr<double>)D.u, v = (gptr<double>)D.v, w = (gptr<double>)D.w;
+    const gptr<double> us = (gptr<double>)D.us, vs = (gptr<double>)D.vs, ws = (gptr<double>)D.ws;
+    if (to_u) { u[q] = us[q]; v[q] = vs[q]; w[q] = ws[q]; }
+    else { us[q] = u[q]; vs[q] = v[q]; ws[q] = w[q]; }
 }
 
 }  // namespace
