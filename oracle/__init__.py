@@ -30,7 +30,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
-OLDROYD_B, FENE_P, SARAMITO = 0, 1, 2
+OLDROYD_B, FENE_P, SARAMITO, NEO_HOOKEAN = 0, 1, 2, 3
+WENO5, HOUC5 = 0, 1
 FORCE_NONE, FORCE_CONST_X, FORCE_SIN_X_OF_Y = 0, 1, 2
 
 
@@ -61,6 +62,7 @@ class _Params(ctypes.Structure):
         ("force_amp", ctypes.c_double), ("force_ky", ctypes.c_double),
         ("u_bot", ctypes.c_double), ("u_top", ctypes.c_double),
         ("w_bot", ctypes.c_double), ("w_top", ctypes.c_double),
+        ("adv_scheme", ctypes.c_int), ("kappa", ctypes.c_double),
     ]
 
 
@@ -80,6 +82,9 @@ def _load():
         lib.oracle_predictor.restype = None
         lib.oracle_weno5_line.argtypes = [dp, ctypes.c_int, ctypes.c_double, ctypes.c_double, dp]
         lib.oracle_weno5_line.restype = None
+        lib.oracle_upwind_line.argtypes = [dp, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                           ctypes.c_int, dp]
+        lib.oracle_upwind_line.restype = None
         lib.oracle_stress.argtypes = [pp, dp, dp]
         lib.oracle_stress.restype = None
         lib.oracle_closure.argtypes = [pp, dp, dp, dp]
@@ -128,7 +133,9 @@ class Grid:
 
 @dataclass
 class Rheology:
-    """Coefficients of Eq. (NS) and Table 1 (rho, mu_s, mu_p, lambda, tau_y, L^2)."""
+    """Coefficients of Eq. (NS) and Table 1 (rho, mu_s, mu_p, lambda, tau_y, L^2), the stress
+    advection scheme (WENO5 or HOUC5, Sec. 3) and the artificial diffusion coefficient kappa of
+    Sec. 3.1 (0: off).  Neo-Hookean: G = mu_p / lambda."""
     model: int = OLDROYD_B
     rho: float = 1.0
     mu_s: float = 0.0
@@ -136,12 +143,22 @@ class Rheology:
     lam: float = 1.0
     tau_y: float = 0.0
     L2: float = 1.0e4
+    adv: int = WENO5
+    kappa: float = 0.0
 
 
 def _params(g: Grid, r: Rheology, forcing=(FORCE_NONE, 0.0, 0.0), walls_uv=(0.0, 0.0, 0.0, 0.0)):
     return _Params(g.nx, g.ny, g.nz, int(g.walls), g.dx, g.dy, g.dz, g.y0, r.model, r.rho, r.mu_s,
                    r.mu_p, r.lam, r.tau_y, r.L2, int(forcing[0]), float(forcing[1]),
-                   float(forcing[2]), *map(float, walls_uv))
+                   float(forcing[2]), *map(float, walls_uv), int(r.adv), float(r.kappa))
+
+
+def upwind_line(f: np.ndarray, h: float, vel: float, scheme: int = WENO5) -> np.ndarray:
+    """Periodic upwind derivative of a 1D array with the oracle's WENO5 or HOUC5 stencil."""
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    out = np.empty_like(f)
+    _load().oracle_upwind_line(_ptr(f), f.size, float(h), float(vel), int(scheme), _ptr(out))
+    return out
 
 
 def weno5_line(f: np.ndarray, h: float, vel: float) -> np.ndarray:

@@ -8,7 +8,9 @@
  *   - the generic conformation-tensor transport, Sec. 2 Eq. (SRM2), closed per model by Table 1;
  *   - the deviatoric stress norm of the Saramito model, Sec. 2 (the |tau^d| definition);
  *   - the spatial discretisation of Sec. 3 (staggered uniform grid, second-order central
- *     differences, fifth-order WENO for the stress advection, Sec. 3.1);
+ *     differences, fifth-order WENO or HOUC for the stress advection, Sec. 3 and 3.1);
+ *   - the local artificial diffusion of Sec. 3.1, added to Eq. (SRM2) where det B < 0 or, for
+ *     FENE-P, tr B >= 0.95 L^2, with a caller-given coefficient (the paper tunes it per case);
  *   - the Adams-Bashforth predictor of Sec. 3.2.2, Eqs. (ab2tau), (ab2), (rt), (ru), with rho
  *     constant, g = 0 (absorbed in the pressure) and f a prescribed body force.
  * The pressure projection, Eqs. (var poisson) and (projection), is done by the Python side of
@@ -20,6 +22,11 @@
  *   velocity >= 0 takes the left-biased stencil;
  *   Saramito: tau^d = tau - tr(tau)/3 I, F = 1 when tau_y == 0, else F = 0 when |tau^d| <= tau_y;
  *   FENE-P stress tau = (mu_p/lambda)(F B - a I), Table 1 solved for tau;
+ *   Neo-Hookean: F = a = 0 and tau = G B with G = mu_p/lambda (Table 1; lambda enters nowhere
+ *   else);
+ *   HOUC: the fifth-order upstream-central stencil, upwinded like the WENO scheme;
+ *   artificial diffusion: kappa times the 7-point Laplacian of each component of B (ghost rows
+ *   as for the advection), switched on per cell by the state at the start of the step;
  *   walls in y: u, w reflected about the wall velocity, v = 0 on wall faces, B extrapolated
  *   linearly into ghost cells;
  *   AB2 starts with a forward-Euler step when no history exists.
@@ -31,7 +38,8 @@
 #include <math.h>
 #include <stddef.h>
 
-enum { M_OLDROYD_B = 0, M_FENE_P = 1, M_SARAMITO = 2 };
+enum { M_OLDROYD_B = 0, M_FENE_P = 1, M_SARAMITO = 2, M_NEO_HOOKEAN = 3 };
+enum { ADV_WENO5 = 0, ADV_HOUC5 = 1 };
 enum { XX = 0, XY = 1, XZ = 2, YY = 3, YZ = 4, ZZ = 5 };
 
 typedef struct {
@@ -43,6 +51,8 @@ typedef struct {
     int force_kind;       /* 0 none, 1 f_x = amp, 2 f_x = amp*sin(ky*y) */
     double force_amp, force_ky;
     double u_bot, u_top, w_bot, w_top;
+    int adv_scheme;       /* 0 WENO5, 1 HOUC5 */
+    double kappa;         /* artificial diffusion coefficient (0: off) */
 } oracle_params;
 
 static int wrap(int i, int n) { i %= n; return i < 0 ? i + n : i; }
@@ -107,6 +117,8 @@ static void closure(const oracle_params* P, const double b[6], double* F, double
 {
     if (P->model == M_OLDROYD_B) {
         *F = 1.0; *a = 1.0;
+    } else if (P->model == M_NEO_HOOKEAN) {
+        *F = 0.0; *a = 0.0;
     } else if (P->model == M_FENE_P) {
         double tr = b[XX] + b[YY] + b[ZZ];
         *F = P->L2 / (P->L2 - tr);
@@ -139,6 +151,8 @@ static void stress_from_B(const oracle_params* P, const double b[6], double t[6]
         closure(P, b, &F, &a);
         for (int c = 0; c < 6; ++c) t[c] = G * F * b[c];
         t[XX] -= G * a; t[YY] -= G * a; t[ZZ] -= G * a;
+    } else if (P->model == M_NEO_HOOKEAN) {
+        for (int c = 0; c < 6; ++c) t[c] = G * b[c];
     } else {
         for (int c = 0; c < 6; ++c) t[c] = G * b[c];
         t[XX] -= G; t[YY] -= G; t[ZZ] -= G;
@@ -185,15 +199,53 @@ static double weno_upwind(const double f[7], double h, double vel)
                  (f[3] - f[2]) / h, (f[2] - f[1]) / h);
 }
 
-/* Exported for the WENO pins: periodic 1D derivative of f (length n, spacing h), upwinded for
- * a uniform velocity of sign vel. */
-void oracle_weno5_line(const double* f, int n, double h, double vel, double* out)
+/* Fifth-order upstream-central (HOUC) derivative at the middle of f[0..6] (offsets -3..+3):
+ * the six-point stencil (-2, 15, -60, 20, 30, -3)/60h on offsets -3..+2 for vel >= 0, and its
+ * mirror image on offsets +3..-2 for vel < 0. */
+static double houc_upwind(const double f[7], double h, double vel)
+{
+    if (vel >= 0.0)
+        return (-2.0 * f[0] + 15.0 * f[1] - 60.0 * f[2] + 20.0 * f[3] + 30.0 * f[4] - 3.0 * f[5])
+               / (60.0 * h);
+    return (2.0 * f[6] - 15.0 * f[5] + 60.0 * f[4] - 20.0 * f[3] - 30.0 * f[2] + 3.0 * f[1])
+           / (60.0 * h);
+}
+
+static double adv_upwind(const oracle_params* P, const double f[7], double h, double vel)
+{
+    return P->adv_scheme == ADV_HOUC5 ? houc_upwind(f, h, vel) : weno_upwind(f, h, vel);
+}
+
+/* Exported for the advection pins: periodic 1D derivative of f (length n, spacing h),
+ * upwinded for a uniform velocity of sign vel, with WENO5 (scheme 0) or HOUC5 (scheme 1). */
+void oracle_upwind_line(const double* f, int n, double h, double vel, int scheme, double* out)
 {
     for (int i = 0; i < n; ++i) {
         double s[7];
         for (int m = 0; m < 7; ++m) s[m] = f[wrap(i + m - 3, n)];
-        out[i] = weno_upwind(s, h, vel);
+        out[i] = scheme == ADV_HOUC5 ? houc_upwind(s, h, vel) : weno_upwind(s, h, vel);
     }
+}
+
+void oracle_weno5_line(const double* f, int n, double h, double vel, double* out)
+{
+    oracle_upwind_line(f, n, h, vel, ADV_WENO5, out);
+}
+
+/* det B of a symmetric tensor stored as xx, xy, xz, yy, yz, zz */
+static double det6(const double b[6])
+{
+    return b[XX] * (b[YY] * b[ZZ] - b[YZ] * b[YZ]) - b[XY] * (b[XY] * b[ZZ] - b[YZ] * b[XZ])
+         + b[XZ] * (b[XY] * b[YZ] - b[YY] * b[XZ]);
+}
+
+/* Sec. 3.1: local artificial diffusion where B loses positive definiteness (det B < 0) or, for
+ * FENE-P, where tr B reaches 95 % of L^2. */
+static int diffusion_on(const oracle_params* P, const double b[6])
+{
+    if (P->kappa <= 0.0) return 0;
+    if (det6(b) < 0.0) return 1;
+    return P->model == M_FENE_P && b[XX] + b[YY] + b[ZZ] >= 0.95 * P->L2;
 }
 
 /* Exported: extra stress from B on every cell (six planes in, six planes out). */
@@ -255,6 +307,7 @@ static void stress_rhs(const oracle_params* P, const double* u, const double* v,
 
     double F, a;
     closure(P, b, &F, &a);
+    const int diff = diffusion_on(P, b);
 
     for (int c = 0; c < 6; ++c) {
         double sx[7], sy[7], sz[7];
@@ -263,13 +316,19 @@ static void stress_rhs(const oracle_params* P, const double* u, const double* v,
             sy[m] = Bc(P, B, c, i, j + m - 3, k);
             sz[m] = Bc(P, B, c, i, j, k + m - 3);
         }
-        double adv = uc * weno_upwind(sx, dx, uc) + vc * weno_upwind(sy, dy, vc)
-                   + wc * weno_upwind(sz, dz, wc);
+        double adv = uc * adv_upwind(P, sx, dx, uc) + vc * adv_upwind(P, sy, dy, vc)
+                   + wc * adv_upwind(P, sz, dz, wc);
         int p = ia[c], q = ib[c];
         double ucv = 0.0;   /* (L.B + B.L^T)_pq */
         for (int m = 0; m < 3; ++m) ucv += L[p][m] * Bm[m][q] + Bm[p][m] * L[q][m];
         double relax = ((p == q ? a : 0.0) - F * b[c]) / P->lam;
         rt[c] = relax - adv + ucv;
+        if (diff) {
+            double lap = (sx[2] - 2.0 * sx[3] + sx[4]) / (dx * dx)
+                       + (sy[2] - 2.0 * sy[3] + sy[4]) / (dy * dy)
+                       + (sz[2] - 2.0 * sz[3] + sz[4]) / (dz * dz);
+            rt[c] += P->kappa * lap;
+        }
     }
 }
 
