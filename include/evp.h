@@ -5,9 +5,11 @@
  * The method is the single-phase Eulerian part of Izbassarov et al., "Computational modeling of
  * multiphase viscoelastic and elastoviscoplastic flows":
  *   - unknowns u, p and the conformation tensor B of Sec. 2, Eqs. (mainNS) and (SRM2);
- *   - the closures F, a and the B <-> tau relation of Table 1;
+ *   - the closures F, a and the B <-> tau relation of Table 1 (Oldroyd-B, FENE-P, Saramito,
+ *     Neo-Hookean);
  *   - the staggered grid and differences of Sec. 3 (velocities on faces; p and B at centres;
- *     second-order central differences; fifth-order WENO for u.grad(B), Sec. 3.1);
+ *     second-order central differences; fifth-order WENO or HOUC for u.grad(B), Sec. 3 and
+ *     3.1; optional local artificial diffusion of B, Sec. 3.1);
  *   - the Adams-Bashforth step and Chorin projection of Sec. 3.2.2, Eqs. (ab2tau), (ab2), (rt),
  *     (ru), (var poisson), (projection), with constant rho, g = 0 and f a body force; the pressure
  *     equation is solved with FFTs in periodic directions and a tridiagonal solve across walls;
@@ -59,6 +61,11 @@ extern "C" {
 #define EVP_OLDROYD_B 0
 #define EVP_FENE_P    1
 #define EVP_SARAMITO  2
+#define EVP_NEO_HOOKEAN 3      /* elastic solid: F = a = 0, G = mu_p / lambda (Table 1) */
+
+/* advection scheme for u.grad(B) (Sec. 3) */
+#define EVP_WENO5 0            /* fifth-order WENO (default) */
+#define EVP_HOUC5 1            /* fifth-order upstream-central (linear) */
 
 /* body force f of Eq. (NS) */
 #define EVP_FORCE_NONE       0
@@ -135,9 +142,16 @@ int evp_set_stream(evp_grid* g, void* hip_stream);
 
 /* Material of Eq. (NS) and Table 1: density rho > 0, solvent viscosity mu_s >= 0, polymer
  * viscosity mu_p >= 0, relaxation time lambda > 0, yield stress tau_y >= 0 (Saramito only),
- * extensibility L2 > 3 (FENE-P only). */
+ * extensibility L2 > 3 (FENE-P only).  Neo-Hookean: shear modulus G = mu_p / lambda (lambda
+ * enters nowhere else). */
 int evp_set_rheology(evp_grid* g, int model, double rho, double mu_s, double mu_p, double lambda,
                      double tau_y, double L2);
+
+/* Stress transport options: the advection scheme (EVP_WENO5 or EVP_HOUC5, Sec. 3) and the
+ * coefficient kappa >= 0 of the local artificial diffusion of Sec. 3.1, kappa lap(B) added to the
+ * right-hand side of Eq. (SRM2) in cells where det B < 0 or (FENE-P) tr B >= 0.95 L^2, judged on
+ * the state at the start of the step (kappa = 0: off, the default). */
+int evp_set_transport(evp_grid* g, int scheme, double kappa);
 
 /* Body force f of Eq. (NS), one of EVP_FORCE_*. */
 int evp_set_forcing(evp_grid* g, int kind, double amp, double ky);

@@ -16,14 +16,16 @@ import os
 __all__ = ["Grid", "step_batch", "EvpError", "lib", "workspace_bytes", "symbols",
            "OLDROYD_B", "FENE_P", "SARAMITO", "FP64", "MIXED", "PERIODIC", "WALLS",
            "FORCE_NONE", "FORCE_CONST_X", "FORCE_SIN_X_OF_Y", "FREEZE_VELOCITY",
-           "STOP_AFTER_PREDICTOR", "MAX_BATCH", "KERNEL_NAMES", "AB2", "RK3"]
+           "STOP_AFTER_PREDICTOR", "MAX_BATCH", "KERNEL_NAMES", "AB2", "RK3", "NEO_HOOKEAN",
+           "WENO5", "HOUC5"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libevp.so")
 
 PERIODIC, WALLS = 0, 1
 FP64, MIXED = 0, 1
-OLDROYD_B, FENE_P, SARAMITO = 0, 1, 2
+OLDROYD_B, FENE_P, SARAMITO, NEO_HOOKEAN = 0, 1, 2, 3
+WENO5, HOUC5 = 0, 1
 FORCE_NONE, FORCE_CONST_X, FORCE_SIN_X_OF_Y = 0, 1, 2
 AB2, RK3 = 0, 1
 FREEZE_VELOCITY, STOP_AFTER_PREDICTOR = 1, 2
@@ -65,6 +67,7 @@ symbols = {
     "evp_set_stream": (_i, [_vp, _vp]),
     "evp_set_rheology": (_i, [_vp, _i, _d, _d, _d, _d, _d, _d]),
     "evp_set_forcing": (_i, [_vp, _i, _d, _d]),
+    "evp_set_transport": (_i, [_vp, _i, _d]),
     "evp_set_walls": (_i, [_vp, _d, _d, _d, _d]),
     "evp_write_fields": (_i, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "evp_project": (_i, [_vp]),
@@ -162,6 +165,11 @@ class Grid:
     def set_rheology(self, model, rho=1.0, mu_s=0.0, mu_p=0.0, lam=1.0, tau_y=0.0, L2=1.0e4):
         _check(lib.evp_set_rheology(self._h, int(model), rho, mu_s, mu_p, lam, tau_y, L2),
                "evp_set_rheology")
+
+    def set_transport(self, scheme=WENO5, kappa=0.0):
+        """Stress advection scheme (WENO5 or HOUC5, Sec. 3) and artificial diffusion coefficient
+        kappa (Sec. 3.1; 0 = off)."""
+        _check(lib.evp_set_transport(self._h, int(scheme), float(kappa)), "evp_set_transport")
 
     def set_forcing(self, kind, amp=0.0, ky=0.0):
         _check(lib.evp_set_forcing(self._h, int(kind), amp, ky), "evp_set_forcing")

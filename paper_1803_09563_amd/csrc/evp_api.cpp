@@ -254,16 +254,6 @@ void build_tables(const evp_grid* g, std::vector<char>& host, size_t base)
     }
 }
 
-// EVP_PREDICTOR=ref selects the per-cell reference predictor (A/B checks); default: z-marching
-bool use_reference_predictor()
-{
-    static const bool ref = [] {
-        const char* e = std::getenv("EVP_PREDICTOR");
-        return e && std::strcmp(e, "ref") == 0;
-    }();
-    return ref;
-}
-
 int check_grid(evp_grid* g)
 {
     if (!g) return fail(EVP_ERR_ARG, "null grid");
@@ -281,7 +271,7 @@ int predictor_by_model(evp_grid* const* gs, const Batch& b, bool freeze, bool rk
 {
     evp_grid* g0 = gs[0];
     int r = EVP_OK;
-    for (int model = EVP_OLDROYD_B; model <= EVP_SARAMITO && !r; ++model) {
+    for (int model = EVP_OLDROYD_B; model <= EVP_NEO_HOOKEAN && !r; ++model) {
         Batch bm{};
         for (int i = 0; i < 3; ++i) bm.rk[i] = b.rk[i];
         for (int i = 0; i < b.count; ++i)
@@ -293,10 +283,8 @@ int predictor_by_model(evp_grid* const* gs, const Batch& b, bool freeze, bool rk
             }
         if (bm.count == 0) continue;
         r = timed(g0, EVP_K_PREDICTOR, [&] {
-            return use_reference_predictor()
-                       ? evp::launch_predictor_ref(bm, g0->precision, g0->nx, g0->ny, g0->nz, freeze, g0->stream)
-                       : evp::launch_predictor_zm(bm, g0->precision, g0->nx, g0->ny, g0->nz, freeze,
-                                                  g0->stream, g0->bc == EVP_WALLS, model, rk3);
+            return evp::launch_predictor_zm(bm, g0->precision, g0->nx, g0->ny, g0->nz, freeze,
+                                            g0->stream, g0->bc == EVP_WALLS, model, rk3);
         });
     }
     return r;
@@ -481,7 +469,7 @@ int evp_set_rheology(evp_grid* g, int model, double rho, double mu_s, double mu_
                      double tau_y, double L2)
 {
     if (int r = check_grid(g)) return r;
-    if (model != EVP_OLDROYD_B && model != EVP_FENE_P && model != EVP_SARAMITO)
+    if (model != EVP_OLDROYD_B && model != EVP_FENE_P && model != EVP_SARAMITO && model != EVP_NEO_HOOKEAN)
         return fail(EVP_ERR_ARG, "unknown model");
     if (!(rho > 0) || !(mu_s >= 0) || !(mu_p >= 0) || !(lambda > 0) || !(tau_y >= 0) ||
         !std::isfinite(rho) || !std::isfinite(mu_s) || !std::isfinite(mu_p) || !std::isfinite(lambda) ||
@@ -502,6 +490,16 @@ int evp_set_rheology(evp_grid* g, int model, double rho, double mu_s, double mu_
     if (r) return r;
     g->have_rheo = true;
     return EVP_OK;
+}
+
+int evp_set_transport(evp_grid* g, int scheme, double kappa)
+{
+    if (int r = check_grid(g)) return r;
+    if (scheme != EVP_WENO5 && scheme != EVP_HOUC5) return fail(EVP_ERR_ARG, "scheme must be EVP_WENO5 or EVP_HOUC5");
+    if (!(kappa >= 0) || !std::isfinite(kappa)) return fail(EVP_ERR_ARG, "kappa must be finite and >= 0");
+    g->h.adv = scheme;
+    g->h.kappa = kappa;
+    return upload_desc(g);
 }
 
 int evp_set_forcing(evp_grid* g, int kind, double amp, double ky)
@@ -586,8 +584,6 @@ int evp_step_batch(evp_grid* const* grids, int count, double dt, int nsteps, uns
     if (!g0) return fail(EVP_ERR_ARG, "null grid in batch");
     if (g0->integrator == EVP_RK3 && (flags & EVP_STOP_AFTER_PREDICTOR))
         return fail(EVP_ERR_ARG, "EVP_STOP_AFTER_PREDICTOR applies to the AB2 step only");
-    if (g0->integrator == EVP_RK3 && use_reference_predictor())
-        return fail(EVP_ERR_ARG, "the per-cell reference predictor implements the AB2 step only");
     for (int i = 0; i < count; ++i) {
         const evp_grid* g = grids[i];
         if (!g) return fail(EVP_ERR_ARG, "null grid in batch");

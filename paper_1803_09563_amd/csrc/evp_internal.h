@@ -15,8 +15,10 @@ struct Desc {
     int nx, ny, nz, nh;          // cells; nh = nx/2 + 1 complex values per x-spectrum line
     int walls;                   // EVP_WALLS in y?
     int precision;               // EVP_FP64 or EVP_MIXED
-    int model;                   // EVP_OLDROYD_B / EVP_FENE_P / EVP_SARAMITO
+    int model;                   // EVP_OLDROYD_B / EVP_FENE_P / EVP_SARAMITO / EVP_NEO_HOOKEAN
     int force_kind;              // EVP_FORCE_*
+    int adv;                     // EVP_WENO5 / EVP_HOUC5
+    double kappa;                // artificial diffusion coefficient (0: off)
     long long ncell;             // nx*ny*nz
     long long ps;                // element stride between planes of B, RT, RU (256-byte padded)
     double dx, dy, dz, idx, idy, idz, y0;
@@ -56,8 +58,6 @@ constexpr int ST_PARITY = 1;
 constexpr int ST_EULER = 2;
 
 // Host-side launchers (one per kernel family); shape is common to the whole batch.
-hipError_t launch_predictor_ref(const Batch& b, int precision, int nx, int ny, int nz, bool freeze,
-                                hipStream_t s);
 hipError_t launch_predictor_zm(const Batch& b, int precision, int nx, int ny, int nz, bool freeze,
                                hipStream_t s, bool walls, int model, bool rk3);
 hipError_t launch_stress_div(const Batch& b, int precision, int nx, int ny, int nz, bool walls,

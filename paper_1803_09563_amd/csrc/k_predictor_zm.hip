@@ -1,6 +1,5 @@
-// Predictor of the Adams-Bashforth step (Sec. 3.2.2, Eqs. (rt), (ab2tau), (ru), (ab2)) as a
-// z-marching LDS-tiled kernel.  Same arithmetic as the per-cell kernel in k_predictor.hip, laid
-// out for CDNA4:
+// Predictor of the Adams-Bashforth step (Sec. 3.2.2, Eqs. (rt), (ab2tau), (ru), (ab2)) -- or of
+// one Runge-Kutta substep (Sec. 3.3.1) -- as a z-marching LDS-tiled kernel laid out for CDNA4:
 //   * a block of 32 x 8 threads owns a 32 x 8 column of cells and marches along z over a chunk of
 //     planes, so every field is read from HBM about once;
 //   * the seven planes k-3..k+3 that the z-direction WENO needs for the thread's own cell live in
@@ -79,15 +78,19 @@ __device__ __forceinline__ T weno5u(T v1, T v2, T v3, T v4, T v5, T eps2)
     return (w1 * p1 + w2 * p2 + w3 * p3) * fast_rcp(w1 + w2 + w3);
 }
 
-// upwind derivative (times h) at the middle of f0..f6
+// upwind derivative (times h) at the middle of f0..f6: WENO5, or HOUC5 (the fifth-order linear
+// upwind-biased combination; houc is uniform across the block)
 template <typename T>
-__device__ __forceinline__ T weno_up(T f0, T f1, T f2, T f3, T f4, T f5, T f6, T vel, T eps2)
+__device__ __forceinline__ T weno_up(T f0, T f1, T f2, T f3, T f4, T f5, T f6, T vel, T eps2, bool houc)
 {
     const T d0 = f1 - f0, d1 = f2 - f1, d2 = f3 - f2, d3 = f4 - f3, d4 = f5 - f4, d5 = f6 - f5;
     // pick the upwind-side differences with selects, then evaluate one WENO (no divergence)
     const bool pos = vel >= (T)0;
     const T v1 = pos ? d0 : d5, v2 = pos ? d1 : d4, v3 = pos ? d2 : d3;
     const T v4 = pos ? d3 : d2, v5 = pos ? d4 : d1;
+    if (houc)
+        return (T)(2.0 / 60.0) * v1 - (T)(13.0 / 60.0) * v2 + (T)(47.0 / 60.0) * v3
+             + (T)(27.0 / 60.0) * v4 - (T)(3.0 / 60.0) * v5;
     return weno5u<T>(v1, v2, v3, v4, v5, eps2);
 }
 
@@ -128,7 +131,9 @@ __global__ __launch_bounds__(NTH, 2) void k_pred_zm(Batch B, int freeze, int kc)
     // history weights: AB2 (3/2, -1/2; Euler start 1, 0) or the substep's (zeta, xi)
     const T c1 = RK3 ? (T)B.rk[0] : (euler ? (T)1 : (T)1.5);
     const T c2 = euler ? (T)0 : (RK3 ? (T)B.rk[1] : (T)-0.5);
-    constexpr bool fene = MODEL == EVP_FENE_P, sara = MODEL == EVP_SARAMITO;
+    constexpr bool fene = MODEL == EVP_FENE_P, sara = MODEL == EVP_SARAMITO, neo = MODEL == EVP_NEO_HOOKEAN;
+    const bool houc = D.adv == EVP_HOUC5;
+    const T kap = (T)D.kappa;
     const T G = (T)D.G, L2 = (T)D.L2, afene = (T)D.a_fene, il = (T)D.inv_lam, tyld = (T)D.tau_y;
     const T idx = (T)D.idx, idy = (T)D.idy, idz = (T)D.idz;
     const T e2x = (T)(1e-6 * D.dx * D.dx), e2y = (T)(1e-6 * D.dy * D.dy), e2z = (T)(1e-6 * D.dz * D.dz);
@@ -349,6 +354,17 @@ __global__ __launch_bounds__(NTH, 2) void k_pred_zm(Batch B, int freeze, int kc)
                                    + txy * txy + txz * txz + tyz * tyz);
                 F = (tyld == (T)0) ? (T)1 : (nrm > tyld ? (T)1 - tyld / nrm : (T)0);
                 a = F;
+            } else if (neo) {
+                F = (T)0;
+                a = (T)0;
+            }
+            // local artificial diffusion (Sec. 3.1): det B < 0, or tr B >= 0.95 L^2 (FENE-P)
+            bool diffon = false;
+            if (kap > (T)0) {
+                const T b0 = bt[0] + (T)1, b3 = bt[3] + (T)1, b5 = bt[5] + (T)1;
+                const T det = b0 * (b3 * b5 - bt[4] * bt[4]) - bt[1] * (bt[1] * b5 - bt[4] * bt[2])
+                            + bt[2] * (bt[1] * bt[4] - b3 * bt[2]);
+                diffon = det < (T)0 || (fene && b0 + b3 + b5 >= (T)0.95 * L2);
             }
 
             // stress right-hand side (Eq. rt) and AB2 update (Eq. ab2tau)
@@ -358,11 +374,11 @@ __global__ __launch_bounds__(NTH, 2) void k_pred_zm(Batch B, int freeze, int kc)
 #pragma unroll
             for (int cc = 0; cc < 6; ++cc) {
                 const T gx = weno_up<T>(S.B[cc][r][c - 3], S.B[cc][r][c - 2], S.B[cc][r][c - 1], S.B[cc][r][c],
-                                        S.B[cc][r][c + 1], S.B[cc][r][c + 2], S.B[cc][r][c + 3], uc, e2x);
+                                        S.B[cc][r][c + 1], S.B[cc][r][c + 2], S.B[cc][r][c + 3], uc, e2x, houc);
                 const T gy = weno_up<T>(S.B[cc][r - 3][c], S.B[cc][r - 2][c], S.B[cc][r - 1][c], S.B[cc][r][c],
-                                        S.B[cc][r + 1][c], S.B[cc][r + 2][c], S.B[cc][r + 3][c], vc, e2y);
+                                        S.B[cc][r + 1][c], S.B[cc][r + 2][c], S.B[cc][r + 3][c], vc, e2y, houc);
                 const T gz = weno_up<T>(win[0][cc], win[1][cc], win[2][cc], win[3][cc], win[4][cc],
-                                        win[5][cc], win[6][cc], wc, e2z);
+                                        win[5][cc], win[6][cc], wc, e2z, houc);
                 const T adv = uc * gx * idx + vc * gy * idy + wc * gz * idz;
                 const int p = pa[cc], rr = pb[cc];
                 T ucv = L[p][rr] + L[rr][p];
@@ -370,6 +386,10 @@ __global__ __launch_bounds__(NTH, 2) void k_pred_zm(Batch B, int freeze, int kc)
                 for (int m = 0; m < 3; ++m) ucv += L[p][m] * bt[cm[m][rr]] + bt[cm[p][m]] * L[rr][m];
                 const T relax = (((p == rr) ? (a - F) : (T)0) - F * bt[cc]) * il;
                 rtv[cc] = relax - adv + ucv;
+                if (diffon)
+                    rtv[cc] += kap * ((S.B[cc][r][c - 1] - (T)2 * bt[cc] + S.B[cc][r][c + 1]) * (idx * idx)
+                                      + (S.B[cc][r - 1][c] - (T)2 * bt[cc] + S.B[cc][r + 1][c]) * (idy * idy)
+                                      + (win[2][cc] - (T)2 * bt[cc] + win[4][cc]) * (idz * idz));
                 // bound live ranges: finish this component before the next one's LDS reads
                 __asm__ volatile("" ::"v"(rtv[cc]) : "memory");
             }
@@ -505,6 +525,7 @@ hipError_t launch_predictor_zm(const Batch& b, int precision, int nx, int ny, in
     switch (model) {                                                                               \
     case EVP_FENE_P: EVP_LAUNCH(TT, WW, EVP_FENE_P); break;                                       \
     case EVP_SARAMITO: EVP_LAUNCH(TT, WW, EVP_SARAMITO); break;                                   \
+    case EVP_NEO_HOOKEAN: EVP_LAUNCH(TT, WW, EVP_NEO_HOOKEAN); break;                             \
     default: EVP_LAUNCH(TT, WW, EVP_OLDROYD_B); break;                                            \
     }
     if (precision == EVP_MIXED) {

@@ -14,7 +14,8 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-OLDROYD_B, FENE_P, SARAMITO = 0, 1, 2
+OLDROYD_B, FENE_P, SARAMITO, NEO_HOOKEAN = 0, 1, 2, 3
+WENO5, HOUC5 = 0, 1
 FORCE_NONE, FORCE_CONST_X, FORCE_SIN_X_OF_Y = 0, 1, 2
 SEED = 1803
 
@@ -51,6 +52,8 @@ class Workload:
     noise: float = 0.0
     seed: int = SEED
     project_initial: bool = False
+    adv: int = WENO5             # stress advection scheme
+    kappa: float = 0.0           # artificial diffusion coefficient (0: off)
     extra: dict = field(default_factory=dict)
 
     @property

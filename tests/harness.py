@@ -10,7 +10,7 @@ from paper_1803_09563_amd import inputs
 
 def oracle_solver(wl: inputs.Workload):
     g = oracle.Grid(wl.nx, wl.ny, wl.nz, wl.lx, wl.ly, wl.lz, walls=wl.walls)
-    r = oracle.Rheology(**wl.rheology())
+    r = oracle.Rheology(**wl.rheology(), adv=wl.adv, kappa=wl.kappa)
     return oracle.Solver(g, r, forcing=wl.force, walls_uv=wl.wall_velocity)
 
 
@@ -21,6 +21,7 @@ def gpu_grid(wl: inputs.Workload, precision=None, stream=None):
                  stream=stream)
     G.set_rheology(**wl.rheology())
     G.set_forcing(*wl.force)
+    G.set_transport(wl.adv, wl.kappa)
     if wl.walls:
         G.set_walls(*wl.wall_velocity)
     return G
