@@ -64,6 +64,7 @@ def _args():
     ap.add_argument("--cpu-steps", type=int, default=0, help="oracle steps (0 = size to ~15 s)")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-rk3", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=500)
     ap.add_argument("--quiet", action="store_true")
     return ap.parse_args()
@@ -74,22 +75,27 @@ def _log(msg, quiet=False):
         print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def run_gpu(wl, precision, steps, warmup, quiet, integrator="ab2"):
+def run_gpu(wl, precision, steps, warmup, quiet, integrator="ab2", adv=0, kappa=0.0, model=None):
     import torch
     import paper_1803_09563_amd as evp
     from paper_1803_09563_amd import inputs
 
     prec = evp.MIXED if precision == "mixed" else evp.FP64
     G = evp.Grid(wl.nx, wl.ny, wl.nz, wl.lx, wl.ly, wl.lz, walls=wl.walls, precision=prec)
-    G.set_rheology(**wl.rheology())
+    rh = wl.rheology()
+    if model is not None:
+        rh["model"] = model
+    G.set_rheology(**rh)
     G.set_forcing(*wl.force)
     G.set_integrator(integrator)
+    G.set_transport(adv, kappa)
     u, v, w, B = [torch.from_numpy(a).cuda() for a in inputs.initial_fields(wl)]
     G.write_fields(u, v, w, B)
     G.project()
     G.step(wl.dt, warmup)
     torch.cuda.synchronize()
-    _log(f"{precision} {integrator}: warmup {warmup} steps done", quiet)
+    tag = f"{precision} {integrator} adv={adv} kappa={kappa} model={rh['model']}"
+    _log(f"{tag}: warmup {warmup} steps done", quiet)
 
     stream = G.stream
     t0 = torch.cuda.Event(enable_timing=True)
@@ -102,7 +108,7 @@ def run_gpu(wl, precision, steps, warmup, quiet, integrator="ab2"):
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
     ms = t0.elapsed_time(t1)
-    _log(f"{precision} {integrator}: timed {steps} steps in {ms:.2f} ms (wall {wall * 1e3:.2f} ms)", quiet)
+    _log(f"{tag}: timed {steps} steps in {ms:.2f} ms (wall {wall * 1e3:.2f} ms)", quiet)
 
     # per-kernel HIP-event timing on the library's stream, over a second timed region
     G.profile(True)
@@ -232,6 +238,18 @@ def main():
                                         for k, v in rk["prof"].items() if v["launches"]},
                       "stress_div_hbm_frac": STRESS_DIV_BYTES["fp64"] * wl.ncell / (sd_ms * 1e-3)
                       / 1e9 / HBM_PEAK_GBS}
+    if not a.no_variants:
+        # stress-transport variants on the same workload (FP64 AB2): HOUC5 advection, artificial
+        # diffusion switched on (kappa > 0; the trigger test runs in every cell), Neo-Hookean
+        out["variants"] = {}
+        n_v = max(a.steps // 2, 1)
+        for name, kw in (("houc5", dict(adv=1)), ("artificial_diffusion", dict(kappa=1e-3)),
+                         ("neo_hookean", dict(model=3))):
+            r = run_gpu(wl, "fp64", n_v, a.warmup, a.quiet, **kw)
+            pk_v = r["prof"]["predictor"]
+            out["variants"][name] = {"value": wl.ncell * n_v / (r["ms"] * 1e-3),
+                                     "unit": "cell-steps/s", "steps": n_v,
+                                     "predictor_avg_us": pk_v["ms"] / max(pk_v["launches"], 1) * 1e3}
     if not a.no_serving:
         out["serving"] = serving(a.serving_requests, a.quiet)
     if not a.no_cpu_baseline:

@@ -350,6 +350,7 @@ class Solver:
         self.RU = np.zeros((3,) + shp)
         self.have_hist = False
         self.nstep = 0
+        self.alpha = None
 
     def _p(self):
         return _params(self.g, self.r, self.forcing, self.walls_uv)
@@ -369,6 +370,24 @@ class Solver:
             self.RT = np.array(hist[:6], dtype=np.float64, copy=True)
             self.RU = np.array(hist[6:9], dtype=np.float64, copy=True)
             self.have_hist = True
+
+    def set_solid(self, alpha=None):
+        """Solid volume fractions (alpha_u, alpha_v, alpha_w) around the u-, v- and w-points of
+        the volume-penalisation immersed boundary method, Sec. 3.3.2, Eqs. (Vol) and
+        (forceAdded), for non-moving solids (u_s = 0).  None removes the solid."""
+        self.alpha = None if alpha is None else [np.array(a, dtype=np.float64, copy=True)
+                                                 for a in alpha]
+
+    def _penalise(self, dt, us, vs, ws):
+        """Eq. (Vol) with u_s = 0: f = rho alpha (u_s - u*) / dt, u** = u* + dt f / rho."""
+        if self.alpha is None:
+            return us, vs, ws
+        rho = self.r.rho
+        out = []
+        for a, x in zip(self.alpha, (us, vs, ws)):
+            f = rho * a * (0.0 - x) / dt
+            out.append(x + dt * f / rho)
+        return out
 
     def project(self, dt: float = 1.0):
         """Make u discretely solenoidal (used once on initial data)."""
@@ -393,6 +412,8 @@ class Solver:
             self.B, self.RT, self.RU = Bn, RT, RU
             self.have_hist = True
             self.nstep += 1
+            if not flags & self.FREEZE_VELOCITY:
+                us, vs, ws = self._penalise(dt, us, vs, ws)
             if flags & self.STOP_AFTER_PREDICTOR:
                 self.u, self.v, self.w = us, vs, ws
                 continue
@@ -410,7 +431,9 @@ class Solver:
         u^k = u* - 2 alpha dt grad(psi) / rho                                  (Eqs. NS-num2, NS-num3)
         The viscous term is taken explicitly at k-1 with weight 2 alpha (the paper's superscript k
         on it would need an implicit solve it does not describe); the stress divergence uses
-        B^k, known from the stress update of the same substep."""
+        B^k, known from the stress update of the same substep.  With a solid (``set_solid``) the
+        penalisation of Eq. (Vol) acts on the prediction from the momentum terms, before the old
+        pressure gradient -2 alpha dt grad p^{k-1} / rho is added."""
         g, rh = self.g, self.r
         rho = rh.rho
         f = body_force(g, self.forcing)
@@ -428,11 +451,16 @@ class Solver:
                 _, _, _, Tk = terms(g, rh, self.u, self.v, self.w, Bk, self.forcing, self.walls_uv)
                 gx, gy, gz = gradient(g, self.p)
                 G = np.stack([gx, gy, gz])
-                RU = -ze * A1 - (xi * A2 if A2 is not None else 0.0) - 2 * al * G / rho \
+                # RU of Eq. (NS-num1) in two parts: the momentum terms RM and the old pressure
+                # gradient; u* = (u + dt RM) - dt 2 alpha grad p^{k-1} / rho, the solid
+                # penalisation (if any) acting on the first part
+                RM = -ze * A1 - (xi * A2 if A2 is not None else 0.0) \
                     + (2 * al * V1 + al * (Tk + T1) + 2 * al * f) / rho
-                us = self.u + dt * RU[0]
-                vs = self.v + dt * RU[1]
-                ws = self.w + dt * RU[2]
+                us, vs, ws = self._penalise(dt, self.u + dt * RM[0], self.v + dt * RM[1],
+                                            self.w + dt * RM[2])
+                us = us - dt * (2 * al * G[0] / rho)
+                vs = vs - dt * (2 * al * G[1] / rho)
+                ws = ws - dt * (2 * al * G[2] / rho)
                 if g.walls:
                     vs[:, -1, :] = 0.0
                 dte = 2 * al * dt

@@ -156,6 +156,38 @@ def initial_fields(wl: Workload):
     return u, v, w, B
 
 
+def solid_fractions(wl: Workload, inside, sub: int = 3):
+    """Solid volume fractions (alpha_u, alpha_v, alpha_w) of a fixed obstacle around the u-, v-
+    and w-points: the share of sub^3 sample points of each velocity point's cell-sized control
+    volume for which inside(x, y, z) is true.  Pure geometry (input of the immersed boundary)."""
+    nz, ny, nx = wl.shape
+    dx, dy, dz = wl.dx, wl.dy, wl.dz
+    off = (np.arange(sub) + 0.5) / sub - 0.5
+    out = []
+    for shift in ((1.0, 0.5, 0.5), (0.5, 1.0, 0.5), (0.5, 0.5, 1.0)):
+        x = (np.arange(nx) + shift[0]) * dx
+        y = wl.y0 + (np.arange(ny) + shift[1]) * dy
+        a = np.zeros(wl.shape)
+        for k in range(nz):
+            z = (k + shift[2]) * dz
+            cnt = np.zeros((ny, nx))
+            for oz in off:
+                for oy in off:
+                    for ox in off:
+                        cnt += inside(x[None, :] + ox * dx, y[:, None] + oy * dy, z + oz * dz)
+            a[k] = cnt / sub ** 3
+        out.append(a)
+    if wl.walls:
+        out[1][:, -1, :] = 0.0
+    return out
+
+
+def sphere(center, radius):
+    """inside() of a sphere (no periodic images)."""
+    cx, cy, cz = center
+    return lambda x, y, z: (x - cx) ** 2 + (y - cy) ** 2 + (z - cz) ** 2 <= radius ** 2
+
+
 def random_state(shape, seed, amp_u=0.3, amp_b=0.05, walls=False):
     """A generic random state (for parity tests on arbitrary shapes): noise velocities and a
     symmetric positive-definite perturbation of B = I."""
