@@ -13,6 +13,8 @@
  *   - the Adams-Bashforth step and Chorin projection of Sec. 3.2.2, Eqs. (ab2tau), (ab2), (rt),
  *     (ru), (var poisson), (projection), with constant rho, g = 0 and f a body force; the pressure
  *     equation is solved with FFTs in periodic directions and a tridiagonal solve across walls;
+ *   - fixed obstacles by the volume-penalisation immersed boundary of Sec. 3.3.2, Eqs. (Vol) and
+ *     (forceAdded);
  *   - alternatively the low-storage three-substep Runge-Kutta step of Sec. 3.3.1, Eqs. (RK-rt),
  *     (NS-num1), (rk3tau), (rk3), (NS-num2), (NS-num3), with the coefficients of Eq. (RK).
  *
@@ -101,7 +103,8 @@ extern "C" {
 #define EVP_K_IFFTX     5      /* inverse x transform -> p */
 #define EVP_K_CORRECT   6      /* u = u* - (dt/rho) grad p */
 #define EVP_K_STRESS_DIV 7     /* RK3: u* += dt (alpha/rho) div tau(B^k) */
-#define EVP_K_COUNT     8
+#define EVP_K_PENALISE  8      /* AB2 with a solid: u** = (1 - alpha) u* */
+#define EVP_K_COUNT     9
 
 typedef struct evp_grid evp_grid;
 
@@ -152,6 +155,15 @@ int evp_set_rheology(evp_grid* g, int model, double rho, double mu_s, double mu_
  * right-hand side of Eq. (SRM2) in cells where det B < 0 or (FENE-P) tr B >= 0.95 L^2, judged on
  * the state at the start of the step (kappa = 0: off, the default). */
 int evp_set_transport(evp_grid* g, int scheme, double kappa);
+
+/* Fixed obstacles (Sec. 3.3.2, volume-penalisation immersed boundary): alpha_u, alpha_v, alpha_w
+ * are the solid volume fractions (0 fluid .. 1 solid) around the u-, v- and w-points, dense FP64
+ * device arrays [nz][ny][nx] owned by the caller and read by every later step until replaced, so
+ * they must stay valid and unchanged while set.  Each step then uses u** = (1 - alpha) u* (Eq.
+ * forceAdded, solid velocity 0) in place of the predicted velocity u*; under RK3 the fraction
+ * multiplies the prediction from the momentum terms (the projection then yields p^k).  All three
+ * NULL removes the obstacle; values are not checked. */
+int evp_set_solid(evp_grid* g, const double* alpha_u, const double* alpha_v, const double* alpha_w);
 
 /* Body force f of Eq. (NS), one of EVP_FORCE_*. */
 int evp_set_forcing(evp_grid* g, int kind, double amp, double ky);

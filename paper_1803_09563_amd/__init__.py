@@ -32,7 +32,7 @@ FREEZE_VELOCITY, STOP_AFTER_PREDICTOR = 1, 2
 READ_U, READ_V, READ_W, READ_P, READ_B, READ_HIST = 1, 2, 4, 8, 16, 32
 MAX_BATCH = 32
 KERNEL_NAMES = ("predictor", "div_fftx", "fft_fwd", "solve", "fft_inv", "ifftx", "correct",
-                "stress_div")
+                "stress_div", "penalise")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_1803_09563_amd/build.py` "
@@ -68,6 +68,7 @@ symbols = {
     "evp_set_rheology": (_i, [_vp, _i, _d, _d, _d, _d, _d, _d]),
     "evp_set_forcing": (_i, [_vp, _i, _d, _d]),
     "evp_set_transport": (_i, [_vp, _i, _d]),
+    "evp_set_solid": (_i, [_vp, _vp, _vp, _vp]),
     "evp_set_walls": (_i, [_vp, _d, _d, _d, _d]),
     "evp_write_fields": (_i, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "evp_project": (_i, [_vp]),
@@ -170,6 +171,19 @@ class Grid:
         """Stress advection scheme (WENO5 or HOUC5, Sec. 3) and artificial diffusion coefficient
         kappa (Sec. 3.1; 0 = off)."""
         _check(lib.evp_set_transport(self._h, int(scheme), float(kappa)), "evp_set_transport")
+
+    def set_solid(self, alpha=None):
+        """Fixed obstacle (Sec. 3.3.2): alpha = (alpha_u, alpha_v, alpha_w) solid volume fractions
+        around the velocity points (float64 CUDA tensors of the grid's shape, kept referenced
+        here while set), or None to remove it."""
+        if alpha is None:
+            _check(lib.evp_set_solid(self._h, None, None, None), "evp_set_solid")
+            self._solid = None
+            return
+        s = self.shape
+        ptrs = [_dptr(a, s, n) for a, n in zip(alpha, ("alpha_u", "alpha_v", "alpha_w"))]
+        _check(lib.evp_set_solid(self._h, *ptrs), "evp_set_solid")
+        self._solid = tuple(alpha)
 
     def set_forcing(self, kind, amp=0.0, ky=0.0):
         _check(lib.evp_set_forcing(self._h, int(kind), amp, ky), "evp_set_forcing")

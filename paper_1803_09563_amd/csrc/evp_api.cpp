@@ -265,17 +265,19 @@ constexpr double kRkAlpha[3] = {4.0 / 15.0, 1.0 / 15.0, 1.0 / 6.0};
 constexpr double kRkZeta[3] = {8.0 / 15.0, 5.0 / 12.0, 3.0 / 4.0};
 constexpr double kRkXi[3] = {0.0, -17.0 / 60.0, -5.0 / 12.0};
 
-// The predictor launched once per constitutive model present in the batch, so a grid's
-// arithmetic is the same alone and in any batch.
+// The predictor is specialised per constitutive model and advection scheme: one launch per
+// (model, scheme) pair present in the batch, so a grid's arithmetic is the same alone and in any
+// batch.
 int predictor_by_model(evp_grid* const* gs, const Batch& b, bool freeze, bool rk3)
 {
     evp_grid* g0 = gs[0];
     int r = EVP_OK;
-    for (int model = EVP_OLDROYD_B; model <= EVP_NEO_HOOKEAN && !r; ++model) {
+    for (int variant = 0; variant < 2 * (EVP_NEO_HOOKEAN + 1) && !r; ++variant) {
+        const int model = variant >> 1, adv = variant & 1;
         Batch bm{};
         for (int i = 0; i < 3; ++i) bm.rk[i] = b.rk[i];
         for (int i = 0; i < b.count; ++i)
-            if (gs[i]->h.model == model) {
+            if (gs[i]->h.model == model && gs[i]->h.adv == adv) {
                 bm.d[bm.count] = b.d[i];
                 bm.dt[bm.count] = b.dt[i];
                 bm.state[bm.count] = b.state[i];
@@ -284,7 +286,8 @@ int predictor_by_model(evp_grid* const* gs, const Batch& b, bool freeze, bool rk
         if (bm.count == 0) continue;
         r = timed(g0, EVP_K_PREDICTOR, [&] {
             return evp::launch_predictor_zm(bm, g0->precision, g0->nx, g0->ny, g0->nz, freeze,
-                                            g0->stream, g0->bc == EVP_WALLS, model, rk3);
+                                            g0->stream, g0->bc == EVP_WALLS, model, rk3,
+                                            adv == EVP_HOUC5);
         });
     }
     return r;
@@ -348,6 +351,12 @@ int enqueue_steps(evp_grid* const* gs, int count, double dt, int nsteps, unsigne
         }
         int r = predictor_by_model(gs, b, freeze, false);
         if (r) return r;
+        bool solid = false;
+        for (int i = 0; i < count; ++i) solid |= gs[i]->h.alpha[0] != nullptr;
+        if (solid && !freeze) {
+            r = timed(g0, EVP_K_PENALISE, [&] { return evp::launch_penalise(b, g0->nx, g0->ny, g0->nz, g0->stream); });
+            if (r) return r;
+        }
         if (stop && !freeze) {
             hipError_t e = evp::launch_copy_ustar(b, g0->nx, g0->ny, g0->nz, true, g0->stream);
             if (e != hipSuccess) return hip_fail(e, "copy u*");
@@ -499,6 +508,17 @@ int evp_set_transport(evp_grid* g, int scheme, double kappa)
     if (!(kappa >= 0) || !std::isfinite(kappa)) return fail(EVP_ERR_ARG, "kappa must be finite and >= 0");
     g->h.adv = scheme;
     g->h.kappa = kappa;
+    return upload_desc(g);
+}
+
+int evp_set_solid(evp_grid* g, const double* alpha_u, const double* alpha_v, const double* alpha_w)
+{
+    if (int r = check_grid(g)) return r;
+    const int n = (alpha_u != nullptr) + (alpha_v != nullptr) + (alpha_w != nullptr);
+    if (n != 0 && n != 3) return fail(EVP_ERR_ARG, "alpha_u, alpha_v, alpha_w: all three or none");
+    g->h.alpha[0] = alpha_u;
+    g->h.alpha[1] = alpha_v;
+    g->h.alpha[2] = alpha_w;
     return upload_desc(g);
 }
 

@@ -19,6 +19,7 @@ struct Desc {
     int force_kind;              // EVP_FORCE_*
     int adv;                     // EVP_WENO5 / EVP_HOUC5
     double kappa;                // artificial diffusion coefficient (0: off)
+    const double* alpha[3];      // solid volume fractions at u, v, w points (caller's; null: none)
     long long ncell;             // nx*ny*nz
     long long ps;                // element stride between planes of B, RT, RU (256-byte padded)
     double dx, dy, dz, idx, idy, idz, y0;
@@ -59,9 +60,10 @@ constexpr int ST_EULER = 2;
 
 // Host-side launchers (one per kernel family); shape is common to the whole batch.
 hipError_t launch_predictor_zm(const Batch& b, int precision, int nx, int ny, int nz, bool freeze,
-                               hipStream_t s, bool walls, int model, bool rk3);
+                               hipStream_t s, bool walls, int model, bool rk3, bool houc);
 hipError_t launch_stress_div(const Batch& b, int precision, int nx, int ny, int nz, bool walls,
                              hipStream_t s);
+hipError_t launch_penalise(const Batch& b, int nx, int ny, int nz, hipStream_t s);
 int predictor_chunk(int nx, int ny, int nz);
 hipError_t launch_div_fftx(const Batch& b, int nx, int ny, int nz, hipStream_t s);
 hipError_t launch_fft_strided(const Batch& b, int nx, int ny, int nz, int axis, bool inverse,

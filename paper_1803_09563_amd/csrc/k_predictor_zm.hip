@@ -79,19 +79,20 @@ __device__ __forceinline__ T weno5u(T v1, T v2, T v3, T v4, T v5, T eps2)
 }
 
 // upwind derivative (times h) at the middle of f0..f6: WENO5, or HOUC5 (the fifth-order linear
-// upwind-biased combination; houc is uniform across the block)
-template <typename T>
-__device__ __forceinline__ T weno_up(T f0, T f1, T f2, T f3, T f4, T f5, T f6, T vel, T eps2, bool houc)
+// upwind-biased combination)
+template <typename T, bool HOUC>
+__device__ __forceinline__ T weno_up(T f0, T f1, T f2, T f3, T f4, T f5, T f6, T vel, T eps2)
 {
     const T d0 = f1 - f0, d1 = f2 - f1, d2 = f3 - f2, d3 = f4 - f3, d4 = f5 - f4, d5 = f6 - f5;
     // pick the upwind-side differences with selects, then evaluate one WENO (no divergence)
     const bool pos = vel >= (T)0;
     const T v1 = pos ? d0 : d5, v2 = pos ? d1 : d4, v3 = pos ? d2 : d3;
     const T v4 = pos ? d3 : d2, v5 = pos ? d4 : d1;
-    if (houc)
+    if constexpr (HOUC)
         return (T)(2.0 / 60.0) * v1 - (T)(13.0 / 60.0) * v2 + (T)(47.0 / 60.0) * v3
              + (T)(27.0 / 60.0) * v4 - (T)(3.0 / 60.0) * v5;
-    return weno5u<T>(v1, v2, v3, v4, v5, eps2);
+    else
+        return weno5u<T>(v1, v2, v3, v4, v5, eps2);
 }
 
 // RK3: the substep of Sec. 3.3.1 instead of AB2.  B^k = B^{k-1} + dt (zeta RT^{k-1} + xi RT^{k-2});
@@ -99,7 +100,9 @@ __device__ __forceinline__ T weno_up(T f0, T f1, T f2, T f3, T f4, T f5, T f6, T
 // B^k is complete) and the pressure gradient (the projection then yields p^k itself), and keeps
 // the advection term as the history: u~ = u + dt [-zeta A^{k-1} - xi A^{k-2}
 // + (2 alpha (mu_s lap u + f) + alpha div tau^{k-1}) / rho].
-template <typename T, bool WALLS, int MODEL, bool RK3>
+// HOUC: fifth-order upstream-central advection instead of WENO5 (a separate instantiation, so
+// the WENO kernel's register allocation is not shared with the other scheme).
+template <typename T, bool WALLS, int MODEL, bool RK3, bool HOUC>
 __global__ __launch_bounds__(NTH, 2) void k_pred_zm(Batch B, int freeze, int kc)
 {
     __shared__ Smem<T> S;
@@ -132,7 +135,6 @@ __global__ __launch_bounds__(NTH, 2) void k_pred_zm(Batch B, int freeze, int kc)
     const T c1 = RK3 ? (T)B.rk[0] : (euler ? (T)1 : (T)1.5);
     const T c2 = euler ? (T)0 : (RK3 ? (T)B.rk[1] : (T)-0.5);
     constexpr bool fene = MODEL == EVP_FENE_P, sara = MODEL == EVP_SARAMITO, neo = MODEL == EVP_NEO_HOOKEAN;
-    const bool houc = D.adv == EVP_HOUC5;
     const T kap = (T)D.kappa;
     const T G = (T)D.G, L2 = (T)D.L2, afene = (T)D.a_fene, il = (T)D.inv_lam, tyld = (T)D.tau_y;
     const T idx = (T)D.idx, idy = (T)D.idy, idz = (T)D.idz;
@@ -371,27 +373,32 @@ __global__ __launch_bounds__(NTH, 2) void k_pred_zm(Batch B, int freeze, int kc)
             const int pa[6] = {0, 0, 0, 1, 1, 2}, pb[6] = {0, 1, 2, 1, 2, 2};
             const int cm[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
             T rtv[6];
+            {
 #pragma unroll
-            for (int cc = 0; cc < 6; ++cc) {
-                const T gx = weno_up<T>(S.B[cc][r][c - 3], S.B[cc][r][c - 2], S.B[cc][r][c - 1], S.B[cc][r][c],
-                                        S.B[cc][r][c + 1], S.B[cc][r][c + 2], S.B[cc][r][c + 3], uc, e2x, houc);
-                const T gy = weno_up<T>(S.B[cc][r - 3][c], S.B[cc][r - 2][c], S.B[cc][r - 1][c], S.B[cc][r][c],
-                                        S.B[cc][r + 1][c], S.B[cc][r + 2][c], S.B[cc][r + 3][c], vc, e2y, houc);
-                const T gz = weno_up<T>(win[0][cc], win[1][cc], win[2][cc], win[3][cc], win[4][cc],
-                                        win[5][cc], win[6][cc], wc, e2z, houc);
-                const T adv = uc * gx * idx + vc * gy * idy + wc * gz * idz;
-                const int p = pa[cc], rr = pb[cc];
-                T ucv = L[p][rr] + L[rr][p];
+                for (int cc = 0; cc < 6; ++cc) {
+                    const T gx = weno_up<T, HOUC>(S.B[cc][r][c - 3], S.B[cc][r][c - 2], S.B[cc][r][c - 1], S.B[cc][r][c],
+                                                  S.B[cc][r][c + 1], S.B[cc][r][c + 2], S.B[cc][r][c + 3], uc, e2x);
+                    const T gy = weno_up<T, HOUC>(S.B[cc][r - 3][c], S.B[cc][r - 2][c], S.B[cc][r - 1][c], S.B[cc][r][c],
+                                                  S.B[cc][r + 1][c], S.B[cc][r + 2][c], S.B[cc][r + 3][c], vc, e2y);
+                    const T gz = weno_up<T, HOUC>(win[0][cc], win[1][cc], win[2][cc], win[3][cc], win[4][cc],
+                                                  win[5][cc], win[6][cc], wc, e2z);
+                    const T adv = uc * gx * idx + vc * gy * idy + wc * gz * idz;
+                    const int p = pa[cc], rr = pb[cc];
+                    T ucv = L[p][rr] + L[rr][p];
 #pragma unroll
-                for (int m = 0; m < 3; ++m) ucv += L[p][m] * bt[cm[m][rr]] + bt[cm[p][m]] * L[rr][m];
-                const T relax = (((p == rr) ? (a - F) : (T)0) - F * bt[cc]) * il;
-                rtv[cc] = relax - adv + ucv;
-                if (diffon)
+                    for (int m = 0; m < 3; ++m) ucv += L[p][m] * bt[cm[m][rr]] + bt[cm[p][m]] * L[rr][m];
+                    const T relax = (((p == rr) ? (a - F) : (T)0) - F * bt[cc]) * il;
+                    rtv[cc] = relax - adv + ucv;
+                    // bound live ranges: finish this component before the next one's LDS reads
+                    __asm__ volatile("" ::"v"(rtv[cc]) : "memory");
+                }
+            }
+            if (diffon) {
+#pragma unroll
+                for (int cc = 0; cc < 6; ++cc)
                     rtv[cc] += kap * ((S.B[cc][r][c - 1] - (T)2 * bt[cc] + S.B[cc][r][c + 1]) * (idx * idx)
                                       + (S.B[cc][r - 1][c] - (T)2 * bt[cc] + S.B[cc][r + 1][c]) * (idy * idy)
                                       + (win[2][cc] - (T)2 * bt[cc] + win[4][cc]) * (idz * idz));
-                // bound live ranges: finish this component before the next one's LDS reads
-                __asm__ volatile("" ::"v"(rtv[cc]) : "memory");
             }
 #pragma unroll
             for (int cc = 0; cc < 6; ++cc) {
@@ -471,10 +478,12 @@ __global__ __launch_bounds__(NTH, 2) void k_pred_zm(Batch B, int freeze, int kc)
 #undef TZ
                 const T ox = euler ? (T)0 : RU[q], oy = euler ? (T)0 : RU[ps + q], oz = euler ? (T)0 : RU[2 * ps + q];
                 if constexpr (RK3) {
+                    // the stress divergence at B^k and any solid penalisation follow in k_stress_div
                     gus[q] = gu[q] + (double)(dt * (mx * irho - c1 * rux - c2 * ox));
                     gvs[q] = vwall ? 0.0 : gv[q] + (double)(dt * (my * irho - c1 * ruy - c2 * oy));
                     gws[q] = gw[q] + (double)(dt * (mz * irho - c1 * ruz - c2 * oz));
                 } else {
+                    // a solid, if any, is applied by k_penalise once u* is complete
                     gus[q] = gu[q] + (double)(dt * (c1 * rux + c2 * ox));
                     gvs[q] = vwall ? 0.0 : gv[q] + (double)(dt * (c1 * ruy + c2 * oy));
                     gws[q] = gw[q] + (double)(dt * (c1 * ruz + c2 * oz));
@@ -510,16 +519,21 @@ int predictor_chunk(int nx, int ny, int nz)
 }
 
 hipError_t launch_predictor_zm(const Batch& b, int precision, int nx, int ny, int nz, bool freeze,
-                               hipStream_t s, bool walls, int model, bool rk3)
+                               hipStream_t s, bool walls, int model, bool rk3, bool houc)
 {
     const int kc = predictor_chunk(nx, ny, nz);
     const int nblk = ((nx + TX - 1) / TX) * ((ny + TY - 1) / TY) * ((nz + kc - 1) / kc);
     dim3 grid(nblk, b.count);
     const int fz = freeze ? 1 : 0;
+#define EVP_LAUNCH2(TT, WW, MM, RR)                                                                \
+    do {                                                                                           \
+        if (houc) hipLaunchKernelGGL((k_pred_zm<TT, WW, MM, RR, true>), grid, dim3(NTH), 0, s, b, fz, kc); \
+        else hipLaunchKernelGGL((k_pred_zm<TT, WW, MM, RR, false>), grid, dim3(NTH), 0, s, b, fz, kc); \
+    } while (0)
 #define EVP_LAUNCH(TT, WW, MM)                                                                     \
     do {                                                                                           \
-        if (rk3) hipLaunchKernelGGL((k_pred_zm<TT, WW, MM, true>), grid, dim3(NTH), 0, s, b, fz, kc); \
-        else hipLaunchKernelGGL((k_pred_zm<TT, WW, MM, false>), grid, dim3(NTH), 0, s, b, fz, kc); \
+        if (rk3) EVP_LAUNCH2(TT, WW, MM, true);                                                    \
+        else EVP_LAUNCH2(TT, WW, MM, false);                                                       \
     } while (0)
 #define EVP_BY_MODEL(TT, WW)                                                                       \
     switch (model) {                                                                               \
@@ -535,6 +549,7 @@ hipError_t launch_predictor_zm(const Batch& b, int precision, int nx, int ny, in
     }
 #undef EVP_BY_MODEL
 #undef EVP_LAUNCH
+#undef EVP_LAUNCH2
     return hipGetLastError();
 }
 

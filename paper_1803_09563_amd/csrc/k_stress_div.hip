@@ -2,7 +2,8 @@
 // stress update has produced B^k everywhere, u* += dt (alpha / rho) div tau(B^k) on every face.
 // Same face stencils as the momentum part of the predictor: tau_aa differenced across the face,
 // the off-diagonal components averaged over the four cells around the face and differenced
-// across it; wall ghost rows of B extrapolated linearly, no update on the top wall v-face.
+// across it; wall ghost rows of B extrapolated linearly, no update on the top wall v-face.  With
+// a solid (Sec. 3.3.2), the completed prediction is then penalised: u** = (1 - alpha) u*.
 //
 // Layout: a block of 32 x 8 threads owns a 32 x 8 column of cells and marches along z over a
 // chunk of planes.  tau (six components, from B - I and the closure) of planes k-1, k, k+1 on the
@@ -52,6 +53,7 @@ __global__ __launch_bounds__(SN) void k_stress_div(Batch B, int kc)
     const T G = (T)D.G, L2 = (T)D.L2, afene = (T)D.a_fene;
     const T idx = (T)D.idx, idy = (T)D.idy, idz = (T)D.idz, qt = (T)0.25;
     const T c = (T)(B.dt[b] * B.rk[2] * D.inv_rho);
+    const bool solid = D.alpha[0] != nullptr;
 
     // source of a box cell (ii, jj): value = wa B[oa] + wb B[ob] (plane-relative offsets)
     struct Src { long long oa, ob; T wa, wb; };
@@ -116,7 +118,12 @@ __global__ __launch_bounds__(SN) void k_stress_div(Batch B, int kc)
     for (int k = k0; k < k1; ++k) {
         const long long q = (long long)k * sxy + (long long)j * nx + i;
         double uo = 0.0, vo = 0.0, wo = 0.0;
-        if (valid) { uo = us[q]; vo = vs[q]; wo = ws[q]; }
+        double pen[3] = {1.0, 1.0, 1.0};         // 1 - alpha of the solid fractions, if any
+        if (valid) {
+            uo = us[q]; vo = vs[q]; wo = ws[q];
+            if (solid)
+                for (int m = 0; m < 3; ++m) pen[m] = 1.0 - ((gptr<const double>)D.alpha[m])[q];
+        }
         load(k + 1, (k + 1) % 3);
         __syncthreads();
         if (valid) {
@@ -128,26 +135,50 @@ __global__ __launch_bounds__(SN) void k_stress_div(Batch B, int kc)
             const T dx_ = (TA(P0, 0, 1, 0) - TA(P0, 0, 0, 0)) * idx
                         + qt * (TA(P0, 1, 0, 1) + TA(P0, 1, 1, 1) - TA(P0, 1, 0, -1) - TA(P0, 1, 1, -1)) * idy
                         + qt * (TA(Pp, 2, 0, 0) + TA(Pp, 2, 1, 0) - TA(Pm, 2, 0, 0) - TA(Pm, 2, 1, 0)) * idz;
-            us[q] = uo + (double)(c * dx_);
+            us[q] = (uo + (double)(c * dx_)) * pen[0];
             // y-face (i, j+1/2, k); the top wall face stays 0
             if (!vwall) {
                 const T dy_ = qt * (TA(P0, 1, 1, 0) + TA(P0, 1, 1, 1) - TA(P0, 1, -1, 0) - TA(P0, 1, -1, 1)) * idx
                             + (TA(P0, 3, 0, 1) - TA(P0, 3, 0, 0)) * idy
                             + qt * (TA(Pp, 4, 0, 0) + TA(Pp, 4, 0, 1) - TA(Pm, 4, 0, 0) - TA(Pm, 4, 0, 1)) * idz;
-                vs[q] = vo + (double)(c * dy_);
+                vs[q] = (vo + (double)(c * dy_)) * pen[1];
             }
             // z-face (i, j, k+1/2)
             const T dz_ = qt * (TA(P0, 2, 1, 0) + TA(Pp, 2, 1, 0) - TA(P0, 2, -1, 0) - TA(Pp, 2, -1, 0)) * idx
                         + qt * (TA(P0, 4, 0, 1) + TA(Pp, 4, 0, 1) - TA(P0, 4, 0, -1) - TA(Pp, 4, 0, -1)) * idy
                         + (TA(Pp, 5, 0, 0) - TA(P0, 5, 0, 0)) * idz;
-            ws[q] = wo + (double)(c * dz_);
+            ws[q] = (wo + (double)(c * dz_)) * pen[2];
 #undef TA
         }
         __syncthreads();
     }
 }
 
+// Volume-penalisation immersed boundary for the AB2 step (Sec. 3.3.2, Eq. forceAdded):
+// u** = (1 - alpha) u* on every face of the grids in the batch that have a solid.  (Under RK3 the
+// same product is fused into k_stress_div.)  A pass of its own so that the predictor's register
+// allocation is not shared with it.
+__global__ __launch_bounds__(256) void k_penalise(Batch B)
+{
+    const Desc& D = *B.d[blockIdx.y];
+    if (D.alpha[0] == nullptr) return;
+    const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (q >= D.ncell) return;
+    const gptr<double> us = (gptr<double>)D.us, vs = (gptr<double>)D.vs, ws = (gptr<double>)D.ws;
+    us[q] *= 1.0 - ((gptr<const double>)D.alpha[0])[q];
+    vs[q] *= 1.0 - ((gptr<const double>)D.alpha[1])[q];
+    ws[q] *= 1.0 - ((gptr<const double>)D.alpha[2])[q];
+}
+
 }  // namespace
+
+hipError_t launch_penalise(const Batch& b, int nx, int ny, int nz, hipStream_t s)
+{
+    const long long ncell = (long long)nx * ny * nz;
+    dim3 grid((unsigned)((ncell + 255) / 256), b.count);
+    hipLaunchKernelGGL(k_penalise, grid, dim3(256), 0, s, b);
+    return hipGetLastError();
+}
 
 hipError_t launch_stress_div(const Batch& b, int precision, int nx, int ny, int nz, bool walls,
                              hipStream_t s)
