@@ -400,16 +400,24 @@ __global__ __launch_bounds__(NTH, 2) void k_pred_zm(Batch B, int freeze, int kc)
                                       + (S.B[cc][r - 1][c] - (T)2 * bt[cc] + S.B[cc][r + 1][c]) * (idy * idy)
                                       + (win[2][cc] - (T)2 * bt[cc] + win[4][cc]) * (idz * idz));
             }
+            // every load of this cell's history and velocity is issued before any store: the
+            // compiler cannot move a load above a store it cannot prove disjoint, and a wait for
+            // a load also waits for the stores issued before it
+            T old[6];
+#pragma unroll
+            for (int cc = 0; cc < 6; ++cc) old[cc] = euler ? (T)0 : RT[cc * ps + q];
+            const double u0 = gu[q], v0 = gv[q], w0 = gw[q];
+            T ox = (T)0, oy = (T)0, oz = (T)0;
+            if (!euler && !freeze) { ox = RU[q]; oy = RU[ps + q]; oz = RU[2 * ps + q]; }
 #pragma unroll
             for (int cc = 0; cc < 6; ++cc) {
-                const T old = euler ? (T)0 : RT[cc * ps + q];
-                Bout[cc * ps + q] = bt[cc] + dt * (c1 * rtv[cc] + c2 * old);
+                Bout[cc * ps + q] = bt[cc] + dt * (c1 * rtv[cc] + c2 * old[cc]);
                 RT[cc * ps + q] = rtv[cc];
             }
 
             __asm__ volatile("" ::: "memory");
             if (freeze) {
-                gus[q] = gu[q]; gvs[q] = gv[q]; gws[q] = gw[q];
+                gus[q] = u0; gvs[q] = v0; gws[q] = w0;
                 RU[q] = (T)0; RU[ps + q] = (T)0; RU[2 * ps + q] = (T)0;
             } else {
                 // stresses of plane k from B - I and the staged factors
@@ -476,17 +484,16 @@ __global__ __launch_bounds__(NTH, 2) void k_pred_zm(Batch B, int freeze, int kc)
                 }
 #undef TK
 #undef TZ
-                const T ox = euler ? (T)0 : RU[q], oy = euler ? (T)0 : RU[ps + q], oz = euler ? (T)0 : RU[2 * ps + q];
                 if constexpr (RK3) {
                     // the stress divergence at B^k and any solid penalisation follow in k_stress_div
-                    gus[q] = gu[q] + (double)(dt * (mx * irho - c1 * rux - c2 * ox));
-                    gvs[q] = vwall ? 0.0 : gv[q] + (double)(dt * (my * irho - c1 * ruy - c2 * oy));
-                    gws[q] = gw[q] + (double)(dt * (mz * irho - c1 * ruz - c2 * oz));
+                    gus[q] = u0 + (double)(dt * (mx * irho - c1 * rux - c2 * ox));
+                    gvs[q] = vwall ? 0.0 : v0 + (double)(dt * (my * irho - c1 * ruy - c2 * oy));
+                    gws[q] = w0 + (double)(dt * (mz * irho - c1 * ruz - c2 * oz));
                 } else {
                     // a solid, if any, is applied by k_penalise once u* is complete
-                    gus[q] = gu[q] + (double)(dt * (c1 * rux + c2 * ox));
-                    gvs[q] = vwall ? 0.0 : gv[q] + (double)(dt * (c1 * ruy + c2 * oy));
-                    gws[q] = gw[q] + (double)(dt * (c1 * ruz + c2 * oz));
+                    gus[q] = u0 + (double)(dt * (c1 * rux + c2 * ox));
+                    gvs[q] = vwall ? 0.0 : v0 + (double)(dt * (c1 * ruy + c2 * oy));
+                    gws[q] = w0 + (double)(dt * (c1 * ruz + c2 * oz));
                 }
                 RU[q] = rux; RU[ps + q] = ruy; RU[2 * ps + q] = ruz;
             }
