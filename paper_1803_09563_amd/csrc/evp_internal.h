@@ -64,7 +64,7 @@ hipError_t launch_predictor_zm(const Batch& b, int precision, int nx, int ny, in
 hipError_t launch_stress_div(const Batch& b, int precision, int nx, int ny, int nz, bool walls,
                              hipStream_t s);
 hipError_t launch_penalise(const Batch& b, int nx, int ny, int nz, hipStream_t s);
-int predictor_chunk(int nx, int ny, int nz);
+int predictor_chunk(int nx, int ny, int nz, bool three_per_cu);
 hipError_t launch_div_fftx(const Batch& b, int nx, int ny, int nz, hipStream_t s);
 hipError_t launch_fft_strided(const Batch& b, int nx, int ny, int nz, int axis, bool inverse,
                               hipStream_t s);

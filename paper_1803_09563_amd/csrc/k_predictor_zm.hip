@@ -103,7 +103,7 @@ __device__ __forceinline__ T weno_up(T f0, T f1, T f2, T f3, T f4, T f5, T f6, T
 // HOUC: fifth-order upstream-central advection instead of WENO5 (a separate instantiation, so
 // the WENO kernel's register allocation is not shared with the other scheme).
 template <typename T, bool WALLS, int MODEL, bool RK3, bool HOUC>
-__global__ __launch_bounds__(NTH, 2) void k_pred_zm(Batch B, int freeze, int kc)
+__global__ __launch_bounds__(NTH, (sizeof(T) == 4 && !WALLS) ? 3 : 2) void k_pred_zm(Batch B, int freeze, int kc)
 {
     __shared__ Smem<T> S;
     const int b = blockIdx.y;
@@ -511,14 +511,15 @@ __global__ __launch_bounds__(NTH, 2) void k_pred_zm(Batch B, int freeze, int kc)
 
 }  // namespace
 
-// planes per block: about two resident blocks per CU on 256 CUs, at least 4 planes per block
-int predictor_chunk(int nx, int ny, int nz)
+// planes per block: about as many blocks as can be resident (two per CU; three for the FP32
+// periodic kernel, whose registers allow three waves per SIMD), at least 4 planes per block
+int predictor_chunk(int nx, int ny, int nz, bool three_per_cu)
 {
-    static const int target = [] {
+    static const int target_env = [] {
         const char* e = std::getenv("EVP_PRED_BLOCKS");
-        const int v = e ? std::atoi(e) : 0;
-        return v > 0 ? v : 512;
+        return e ? std::atoi(e) : 0;
     }();
+    const int target = target_env > 0 ? target_env : (three_per_cu ? 768 : 512);
     const int tiles = ((nx + TX - 1) / TX) * ((ny + TY - 1) / TY);
     int nch = (target + tiles - 1) / tiles;
     nch = max(1, min(nch, nz / 4));
@@ -528,7 +529,7 @@ int predictor_chunk(int nx, int ny, int nz)
 hipError_t launch_predictor_zm(const Batch& b, int precision, int nx, int ny, int nz, bool freeze,
                                hipStream_t s, bool walls, int model, bool rk3, bool houc)
 {
-    const int kc = predictor_chunk(nx, ny, nz);
+    const int kc = predictor_chunk(nx, ny, nz, precision == EVP_MIXED && !walls);
     const int nblk = ((nx + TX - 1) / TX) * ((ny + TY - 1) / TY) * ((nz + kc - 1) / kc);
     dim3 grid(nblk, b.count);
     const int fz = freeze ? 1 : 0;

@@ -406,12 +406,18 @@ __global__ __launch_bounds__(256) void k_correct(Batch B)
 __global__ __launch_bounds__(256) void k_copy_ustar(Batch B, int to_u)
 {
     const Desc& D = *B.d[blockIdx.y];
-    const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
-    if (q >= D.ncell) return;
+    const long long ncell = D.ncell;
     const gptr<double> u = (gptr<double>)D.u, v = (gptr<double>)D.v, w = (gptr<double>)D.w;
     const gptr<double> us = (gptr<double>)D.us, vs = (gptr<double>)D.vs, ws = (gptr<double>)D.ws;
-    if (to_u) { u[q] = us[q]; v[q] = vs[q]; w[q] = ws[q]; }
-    else { us[q] = u[q]; vs[q] = v[q]; ws[q] = w[q]; }
+    const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (q >= ncell) return;
+    if (to_u) {
+        const double a = us[q], b = vs[q], c = ws[q];
+        u[q] = a; v[q] = b; w[q] = c;
+    } else {
+        const double a = u[q], b = v[q], c = w[q];
+        us[q] = a; vs[q] = b; ws[q] = c;
+    }
 }
 
 }  // namespace

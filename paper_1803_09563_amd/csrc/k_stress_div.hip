@@ -165,9 +165,12 @@ __global__ __launch_bounds__(256) void k_penalise(Batch B)
     const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
     if (q >= D.ncell) return;
     const gptr<double> us = (gptr<double>)D.us, vs = (gptr<double>)D.vs, ws = (gptr<double>)D.ws;
-    us[q] *= 1.0 - ((gptr<const double>)D.alpha[0])[q];
-    vs[q] *= 1.0 - ((gptr<const double>)D.alpha[1])[q];
-    ws[q] *= 1.0 - ((gptr<const double>)D.alpha[2])[q];
+    const gptr<const double> au = (gptr<const double>)D.alpha[0], av = (gptr<const double>)D.alpha[1],
+                             aw = (gptr<const double>)D.alpha[2];
+    const double x = us[q], y = vs[q], z = ws[q], a = au[q], b = av[q], c = aw[q];
+    us[q] = x * (1.0 - a);
+    vs[q] = y * (1.0 - b);
+    ws[q] = z * (1.0 - c);
 }
 
 }  // namespace
