@@ -63,6 +63,8 @@ class _Params(ctypes.Structure):
         ("u_bot", ctypes.c_double), ("u_top", ctypes.c_double),
         ("w_bot", ctypes.c_double), ("w_top", ctypes.c_double),
         ("adv_scheme", ctypes.c_int), ("kappa", ctypes.c_double),
+        ("lam_c", ctypes.c_void_p), ("mup_c", ctypes.c_void_p), ("mus_c", ctypes.c_void_p),
+        ("rho_c", ctypes.c_void_p), ("fs", ctypes.c_void_p),
     ]
 
 

@@ -53,6 +53,15 @@ typedef struct {
     double u_bot, u_top, w_bot, w_top;
     int adv_scheme;       /* 0 WENO5, 1 HOUC5 */
     double kappa;         /* artificial diffusion coefficient (0: off) */
+    /* two-phase mixture (Sec. 3.2.1): per-cell lambda, mu_p, mu_s, rho at cell centres (NULL:
+     * the constants above; a per-cell mu_s selects the full div(mu_s (grad u + grad u^T))) and an
+     * extra force density on the faces, three planes x, y, z (NULL: none).  Ghost rows beyond a
+     * wall take the properties of the adjacent interior row. */
+    const double* lam_c;
+    const double* mup_c;
+    const double* mus_c;
+    const double* rho_c;
+    const double* fs;
 } oracle_params;
 
 static int wrap(int i, int n) { i %= n; return i < 0 ? i + n : i; }
@@ -112,8 +121,24 @@ static double Bc(const oracle_params* P, const double* B, int c, int i, int j, i
     return b[at(P, i, j, k)];
 }
 
-/* Table 1: the factors F and a of Eq. (SRM2) for the given B. */
-static void closure(const oracle_params* P, const double b[6], double* F, double* a)
+/* Material property of cell (i,j,k): per-cell array if given, else the constant; ghost rows
+ * copy the nearest interior row. */
+static double prop(const oracle_params* P, const double* arr, double c, int i, int j, int k)
+{
+    if (!arr) return c;
+    i = wrap(i, P->nx); k = wrap(k, P->nz);
+    if (P->walls) j = j < 0 ? 0 : (j >= P->ny ? P->ny - 1 : j);
+    else j = wrap(j, P->ny);
+    return arr[at(P, i, j, k)];
+}
+
+static double G_at(const oracle_params* P, int i, int j, int k)
+{
+    return prop(P, P->mup_c, P->mu_p, i, j, k) / prop(P, P->lam_c, P->lam, i, j, k);
+}
+
+/* Table 1: the factors F and a of Eq. (SRM2) for the given B; G = mu_p / lambda of the cell. */
+static void closure(const oracle_params* P, const double b[6], double G, double* F, double* a)
 {
     if (P->model == M_OLDROYD_B) {
         *F = 1.0; *a = 1.0;
@@ -125,7 +150,6 @@ static void closure(const oracle_params* P, const double b[6], double* F, double
         *a = P->L2 / (P->L2 - 3.0);
     } else {
         /* Saramito: tau = (mu_p/lambda)(B - I); von Mises switch on |tau^d| (Sec. 2). */
-        double G = P->mu_p / P->lam;
         double t[6];
         for (int c = 0; c < 6; ++c) t[c] = G * b[c];
         t[XX] -= G; t[YY] -= G; t[ZZ] -= G;
@@ -143,12 +167,11 @@ static void closure(const oracle_params* P, const double b[6], double* F, double
 }
 
 /* Extra stress tau from B by inverting the B-definitions of Table 1. */
-static void stress_from_B(const oracle_params* P, const double b[6], double t[6])
+static void stress_from_B(const oracle_params* P, const double b[6], double G, double t[6])
 {
-    double G = P->mu_p / P->lam;
     if (P->model == M_FENE_P) {
         double F, a;
-        closure(P, b, &F, &a);
+        closure(P, b, G, &F, &a);
         for (int c = 0; c < 6; ++c) t[c] = G * F * b[c];
         t[XX] -= G * a; t[YY] -= G * a; t[ZZ] -= G * a;
     } else if (P->model == M_NEO_HOOKEAN) {
@@ -163,7 +186,7 @@ static void stress_at(const oracle_params* P, const double* B, int i, int j, int
 {
     double b[6];
     for (int c = 0; c < 6; ++c) b[c] = Bc(P, B, c, i, j, k);
-    stress_from_B(P, b, t);
+    stress_from_B(P, b, G_at(P, i, j, k), t);
 }
 
 /* Fifth-order WENO derivative from the five one-sided difference quotients v1..v5 (the
@@ -255,7 +278,7 @@ void oracle_stress(const oracle_params* P, const double* B, double* tau)
     for (size_t q = 0; q < n; ++q) {
         double b[6], t[6];
         for (int c = 0; c < 6; ++c) b[c] = B[c * n + q];
-        stress_from_B(P, b, t);
+        stress_from_B(P, b, (P->mup_c ? P->mup_c[q] : P->mu_p) / (P->lam_c ? P->lam_c[q] : P->lam), t);
         for (int c = 0; c < 6; ++c) tau[c * n + q] = t[c];
     }
 }
@@ -267,7 +290,8 @@ void oracle_closure(const oracle_params* P, const double* B, double* F, double* 
     for (size_t q = 0; q < n; ++q) {
         double b[6];
         for (int c = 0; c < 6; ++c) b[c] = B[c * n + q];
-        closure(P, b, &F[q], &a[q]);
+        closure(P, b, (P->mup_c ? P->mup_c[q] : P->mu_p) / (P->lam_c ? P->lam_c[q] : P->lam),
+                &F[q], &a[q]);
     }
 }
 
@@ -306,8 +330,9 @@ static void stress_rhs(const oracle_params* P, const double* u, const double* v,
     static const int ia[6] = { 0, 0, 0, 1, 1, 2 }, ib[6] = { 0, 1, 2, 1, 2, 2 };
 
     double F, a;
-    closure(P, b, &F, &a);
+    closure(P, b, G_at(P, i, j, k), &F, &a);
     const int diff = diffusion_on(P, b);
+    const double lam = prop(P, P->lam_c, P->lam, i, j, k);
 
     for (int c = 0; c < 6; ++c) {
         double sx[7], sy[7], sz[7];
@@ -321,7 +346,7 @@ static void stress_rhs(const oracle_params* P, const double* u, const double* v,
         int p = ia[c], q = ib[c];
         double ucv = 0.0;   /* (L.B + B.L^T)_pq */
         for (int m = 0; m < 3; ++m) ucv += L[p][m] * Bm[m][q] + Bm[p][m] * L[q][m];
-        double relax = ((p == q ? a : 0.0) - F * b[c]) / P->lam;
+        double relax = ((p == q ? a : 0.0) - F * b[c]) / lam;
         rt[c] = relax - adv + ucv;
         if (diff) {
             double lap = (sx[2] - 2.0 * sx[3] + sx[4]) / (dx * dx)
@@ -338,6 +363,65 @@ static double force_x(const oracle_params* P, int j)
     if (P->force_kind == 1) return P->force_amp;
     if (P->force_kind == 2) return P->force_amp * sin(P->force_ky * (P->y0 + (j + 0.5) * P->dy));
     return 0.0;
+}
+
+/* Viscous term div(mu_s (grad u + grad u^T)) of Eq. (ru) with a per-cell mu_s (two-phase
+ * mixture): normal viscous stresses 2 mu du_a/dx_a at cell centres, shear stresses
+ * mu (du_a/dx_b + du_b/dx_a) on cell edges with mu the average of the four cells around the edge;
+ * the face value is their difference across the face. */
+static double mu_c(const oracle_params* P, int i, int j, int k)
+{
+    return prop(P, P->mus_c, P->mu_s, i, j, k);
+}
+
+static void viscous_variable(const oracle_params* P, const double* u, const double* v,
+                             const double* w, int i, int j, int k, double Vv[3])
+{
+    const double dx = P->dx, dy = P->dy, dz = P->dz;
+    /* x-face (i+1/2, j, k) */
+    {
+        double t1 = 2.0 * mu_c(P, i + 1, j, k) * (U(P, u, i + 1, j, k) - U(P, u, i, j, k)) / dx;
+        double t0 = 2.0 * mu_c(P, i, j, k) * (U(P, u, i, j, k) - U(P, u, i - 1, j, k)) / dx;
+        double mT = 0.25 * (mu_c(P, i, j, k) + mu_c(P, i + 1, j, k) + mu_c(P, i, j + 1, k) + mu_c(P, i + 1, j + 1, k));
+        double mB = 0.25 * (mu_c(P, i, j, k) + mu_c(P, i + 1, j, k) + mu_c(P, i, j - 1, k) + mu_c(P, i + 1, j - 1, k));
+        double mF = 0.25 * (mu_c(P, i, j, k) + mu_c(P, i + 1, j, k) + mu_c(P, i, j, k + 1) + mu_c(P, i + 1, j, k + 1));
+        double mK = 0.25 * (mu_c(P, i, j, k) + mu_c(P, i + 1, j, k) + mu_c(P, i, j, k - 1) + mu_c(P, i + 1, j, k - 1));
+        double sT = mT * ((U(P, u, i, j + 1, k) - U(P, u, i, j, k)) / dy + (V(P, v, i + 1, j, k) - V(P, v, i, j, k)) / dx);
+        double sB = mB * ((U(P, u, i, j, k) - U(P, u, i, j - 1, k)) / dy + (V(P, v, i + 1, j - 1, k) - V(P, v, i, j - 1, k)) / dx);
+        double sF = mF * ((U(P, u, i, j, k + 1) - U(P, u, i, j, k)) / dz + (W(P, w, i + 1, j, k) - W(P, w, i, j, k)) / dx);
+        double sK = mK * ((U(P, u, i, j, k) - U(P, u, i, j, k - 1)) / dz + (W(P, w, i + 1, j, k - 1) - W(P, w, i, j, k - 1)) / dx);
+        Vv[0] = (t1 - t0) / dx + (sT - sB) / dy + (sF - sK) / dz;
+    }
+    /* y-face (i, j+1/2, k) */
+    if (P->walls && j == P->ny - 1) {
+        Vv[1] = 0.0;
+    } else {
+        double t1 = 2.0 * mu_c(P, i, j + 1, k) * (V(P, v, i, j + 1, k) - V(P, v, i, j, k)) / dy;
+        double t0 = 2.0 * mu_c(P, i, j, k) * (V(P, v, i, j, k) - V(P, v, i, j - 1, k)) / dy;
+        double mR = 0.25 * (mu_c(P, i, j, k) + mu_c(P, i + 1, j, k) + mu_c(P, i, j + 1, k) + mu_c(P, i + 1, j + 1, k));
+        double mL = 0.25 * (mu_c(P, i, j, k) + mu_c(P, i - 1, j, k) + mu_c(P, i, j + 1, k) + mu_c(P, i - 1, j + 1, k));
+        double mF = 0.25 * (mu_c(P, i, j, k) + mu_c(P, i, j + 1, k) + mu_c(P, i, j, k + 1) + mu_c(P, i, j + 1, k + 1));
+        double mK = 0.25 * (mu_c(P, i, j, k) + mu_c(P, i, j + 1, k) + mu_c(P, i, j, k - 1) + mu_c(P, i, j + 1, k - 1));
+        double sR = mR * ((U(P, u, i, j + 1, k) - U(P, u, i, j, k)) / dy + (V(P, v, i + 1, j, k) - V(P, v, i, j, k)) / dx);
+        double sL = mL * ((U(P, u, i - 1, j + 1, k) - U(P, u, i - 1, j, k)) / dy + (V(P, v, i, j, k) - V(P, v, i - 1, j, k)) / dx);
+        double sF = mF * ((V(P, v, i, j, k + 1) - V(P, v, i, j, k)) / dz + (W(P, w, i, j + 1, k) - W(P, w, i, j, k)) / dy);
+        double sK = mK * ((V(P, v, i, j, k) - V(P, v, i, j, k - 1)) / dz + (W(P, w, i, j + 1, k - 1) - W(P, w, i, j, k - 1)) / dy);
+        Vv[1] = (t1 - t0) / dy + (sR - sL) / dx + (sF - sK) / dz;
+    }
+    /* z-face (i, j, k+1/2) */
+    {
+        double t1 = 2.0 * mu_c(P, i, j, k + 1) * (W(P, w, i, j, k + 1) - W(P, w, i, j, k)) / dz;
+        double t0 = 2.0 * mu_c(P, i, j, k) * (W(P, w, i, j, k) - W(P, w, i, j, k - 1)) / dz;
+        double mR = 0.25 * (mu_c(P, i, j, k) + mu_c(P, i + 1, j, k) + mu_c(P, i, j, k + 1) + mu_c(P, i + 1, j, k + 1));
+        double mL = 0.25 * (mu_c(P, i, j, k) + mu_c(P, i - 1, j, k) + mu_c(P, i, j, k + 1) + mu_c(P, i - 1, j, k + 1));
+        double mT = 0.25 * (mu_c(P, i, j, k) + mu_c(P, i, j + 1, k) + mu_c(P, i, j, k + 1) + mu_c(P, i, j + 1, k + 1));
+        double mB = 0.25 * (mu_c(P, i, j, k) + mu_c(P, i, j - 1, k) + mu_c(P, i, j, k + 1) + mu_c(P, i, j - 1, k + 1));
+        double sR = mR * ((U(P, u, i, j, k + 1) - U(P, u, i, j, k)) / dz + (W(P, w, i + 1, j, k) - W(P, w, i, j, k)) / dx);
+        double sL = mL * ((U(P, u, i - 1, j, k + 1) - U(P, u, i - 1, j, k)) / dz + (W(P, w, i, j, k) - W(P, w, i - 1, j, k)) / dx);
+        double sT = mT * ((V(P, v, i, j, k + 1) - V(P, v, i, j, k)) / dz + (W(P, w, i, j + 1, k) - W(P, w, i, j, k)) / dy);
+        double sB = mB * ((V(P, v, i, j - 1, k + 1) - V(P, v, i, j - 1, k)) / dz + (W(P, w, i, j, k) - W(P, w, i, j - 1, k)) / dy);
+        Vv[2] = (t1 - t0) / dz + (sR - sL) / dx + (sT - sB) / dy;
+    }
 }
 
 /* The three momentum terms of Eq. (ru) on the three faces owned by cell (i,j,k): A =
@@ -474,18 +558,28 @@ static void momentum_parts(const oracle_params* P, const double* u, const double
         double divt = (eR - eL) / dx + (eT - eB) / dy + dtzz;
         A[2] = adv; Vv[2] = ms * lap; T[2] = divt;
     }
+    if (P->mus_c) viscous_variable(P, u, v, w, i, j, k, Vv);
 }
 
-/* Momentum right-hand side RU of Eq. (ru) (rho constant, g = 0, no surface tension):
- * RU = -A + (Vv + T + f)/rho, with the body force f on the x-faces. */
+/* Momentum right-hand side RU of Eq. (ru) (g = 0): RU = -A + (Vv + T + f + fs)/rho_face, with
+ * the body force f on the x-faces, the extra face force fs (surface tension) and rho_face the
+ * mean of the two cells beside the face (constant rho for a single phase). */
 static void momentum_rhs(const oracle_params* P, const double* u, const double* v, const double* w,
                          const double* B, int i, int j, int k, double ru[3])
 {
-    double A[3], Vv[3], T[3];
+    double A[3], Vv[3], T[3], f[3] = { force_x(P, j), 0.0, 0.0 };
     momentum_parts(P, u, v, w, B, i, j, k, A, Vv, T);
-    ru[0] = -A[0] + (Vv[0] + T[0] + force_x(P, j)) / P->rho;
-    ru[1] = -A[1] + (Vv[1] + T[1]) / P->rho;
-    ru[2] = -A[2] + (Vv[2] + T[2]) / P->rho;
+    const double r0 = prop(P, P->rho_c, P->rho, i, j, k);
+    const double rf[3] = { 0.5 * (r0 + prop(P, P->rho_c, P->rho, i + 1, j, k)),
+                           0.5 * (r0 + prop(P, P->rho_c, P->rho, i, j + 1, k)),
+                           0.5 * (r0 + prop(P, P->rho_c, P->rho, i, j, k + 1)) };
+    if (P->fs) {
+        const size_t n = (size_t)P->nx * P->ny * P->nz, q = at(P, i, j, k);
+        for (int c = 0; c < 3; ++c) f[c] += P->fs[c * n + q];
+    }
+    for (int c = 0; c < 3; ++c)
+        ru[c] = -A[c] + (Vv[c] + T[c] + f[c]) / (P->rho_c ? rf[c] : P->rho);
+    if (P->walls && j == P->ny - 1) ru[1] = 0.0;
 }
 
 /*
