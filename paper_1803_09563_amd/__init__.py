@@ -13,7 +13,7 @@ from __future__ import annotations
 import ctypes
 import os
 
-__all__ = ["Grid", "step_batch", "EvpError", "lib", "workspace_bytes", "symbols",
+__all__ = ["Grid", "step_batch", "EvpError", "lib", "workspace_bytes", "symbols", "TwoPhaseParams",
            "OLDROYD_B", "FENE_P", "SARAMITO", "FP64", "MIXED", "PERIODIC", "WALLS",
            "FORCE_NONE", "FORCE_CONST_X", "FORCE_SIN_X_OF_Y", "FREEZE_VELOCITY",
            "STOP_AFTER_PREDICTOR", "MAX_BATCH", "KERNEL_NAMES", "AB2", "RK3", "NEO_HOOKEAN",
@@ -32,7 +32,7 @@ FREEZE_VELOCITY, STOP_AFTER_PREDICTOR = 1, 2
 READ_U, READ_V, READ_W, READ_P, READ_B, READ_HIST = 1, 2, 4, 8, 16, 32
 MAX_BATCH = 32
 KERNEL_NAMES = ("predictor", "div_fftx", "fft_fwd", "solve", "fft_inv", "ifftx", "correct",
-                "stress_div", "penalise")
+                "stress_div", "penalise", "level_set", "reinit", "curvature", "momentum2", "split")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_1803_09563_amd/build.py` "
@@ -54,6 +54,14 @@ class _Health(ctypes.Structure):
                 ("trace_ge95", ctypes.c_longlong), ("max_div", _d), ("energy", _d)]
 
 
+class TwoPhaseParams(ctypes.Structure):
+    """evp_two_phase_t: fluid 1 (phi > 0) and fluid 2 (phi < 0) properties, surface tension and the
+    reinitialisation schedule (Sec. 3.2)."""
+    _fields_ = [("rho1", _d), ("rho2", _d), ("mu_s1", _d), ("mu_s2", _d), ("mu_p1", _d),
+                ("mu_p2", _d), ("lam1", _d), ("lam2", _d), ("sigma", _d),
+                ("reinit_every", _i), ("reinit_iters", _i)]
+
+
 class _Profile(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_longlong * len(KERNEL_NAMES)), ("ms", _d * len(KERNEL_NAMES))]
 
@@ -69,6 +77,10 @@ symbols = {
     "evp_set_forcing": (_i, [_vp, _i, _d, _d]),
     "evp_set_transport": (_i, [_vp, _i, _d]),
     "evp_set_solid": (_i, [_vp, _vp, _vp, _vp]),
+    "evp_two_phase_bytes": (ctypes.c_size_t, [_i, _i, _i]),
+    "evp_set_two_phase": (_i, [_vp, ctypes.POINTER(TwoPhaseParams), _vp, ctypes.c_size_t]),
+    "evp_write_level_set": (_i, [_vp, _vp]),
+    "evp_read_level_set": (_i, [_vp, _vp]),
     "evp_set_walls": (_i, [_vp, _d, _d, _d, _d]),
     "evp_write_fields": (_i, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "evp_project": (_i, [_vp]),
@@ -184,6 +196,40 @@ class Grid:
         ptrs = [_dptr(a, s, n) for a, n in zip(alpha, ("alpha_u", "alpha_v", "alpha_w"))]
         _check(lib.evp_set_solid(self._h, *ptrs), "evp_set_solid")
         self._solid = tuple(alpha)
+
+    def set_two_phase(self, params=None, **kw):
+        """Two-phase (bubbly-flow) path of Sec. 3.2 with TwoPhaseParams (or its fields as
+        keywords: rho1, rho2, mu_s1, mu_s2, mu_p1, mu_p2, lam1, lam2, sigma, reinit_every,
+        reinit_iters); None switches back to a single phase.  The level-set workspace is a
+        torch uint8 tensor held here."""
+        torch = _torch()
+        if params is None and not kw:
+            _check(lib.evp_set_two_phase(self._h, None, None, 0), "evp_set_two_phase")
+            self._ws2 = None
+            return
+        if params is None:
+            d = dict(rho1=1.0, rho2=1.0, mu_s1=0.0, mu_s2=0.0, mu_p1=0.0, mu_p2=0.0, lam1=1.0,
+                     lam2=1.0, sigma=0.0, reinit_every=10, reinit_iters=2)
+            d.update(kw)
+            params = TwoPhaseParams(**d)
+        n = int(lib.evp_two_phase_bytes(self.nx, self.ny, self.nz))
+        with torch.cuda.stream(self.stream):
+            buf = torch.empty(n + 256, dtype=torch.uint8, device=self.device)
+        off = (-buf.data_ptr()) % 256
+        _check(lib.evp_set_two_phase(self._h, ctypes.byref(params),
+                                     ctypes.c_void_p(buf.data_ptr() + off), n), "evp_set_two_phase")
+        self._ws2 = buf
+
+    def write_level_set(self, phi):
+        self._keep_phi = phi
+        _check(lib.evp_write_level_set(self._h, _dptr(phi, self.shape, "phi")), "evp_write_level_set")
+
+    def read_level_set(self):
+        torch = _torch()
+        with torch.cuda.stream(self.stream):
+            out = torch.empty(self.shape, dtype=torch.float64, device=self.device)
+        _check(lib.evp_read_level_set(self._h, ctypes.c_void_p(out.data_ptr())), "evp_read_level_set")
+        return out
 
     def set_forcing(self, kind, amp=0.0, ky=0.0):
         _check(lib.evp_set_forcing(self._h, int(kind), amp, ky), "evp_set_forcing")

@@ -15,7 +15,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libevp.so")
 OBJDIR = os.path.join(HERE, "_build")
 
-SOURCES = ["k_predictor_zm.hip", "k_stress_div.hip", "k_projection.hip", "k_misc.hip", "evp_api.cpp"]
+SOURCES = ["k_predictor_zm.hip", "k_stress_div.hip", "k_two_phase.hip", "k_projection.hip", "k_misc.hip",
+           "evp_api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

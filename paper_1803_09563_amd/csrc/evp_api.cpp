@@ -3,6 +3,7 @@
 // per-kernel event timing.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -119,6 +120,10 @@ struct evp_grid {
     int parity;
     int integrator;    // EVP_AB2 or EVP_RK3
     bool have_hist, have_rheo, have_fields;
+    double rho_single;            // rho of evp_set_rheology (the descriptor holds rho_0 in two-phase mode)
+    bool two_phase;               // Sec. 3.2 path on
+    evp_two_phase_t tp;
+    bool p_hist;                  // two-phase: p^n, p^{n-1} valid for the pressure extrapolation
     long long nstep;
     bool prof;
     std::vector<PendingEvent> pending;
@@ -268,7 +273,7 @@ constexpr double kRkXi[3] = {0.0, -17.0 / 60.0, -5.0 / 12.0};
 // The predictor is specialised per constitutive model and advection scheme: one launch per
 // (model, scheme) pair present in the batch, so a grid's arithmetic is the same alone and in any
 // batch.
-int predictor_by_model(evp_grid* const* gs, const Batch& b, bool freeze, bool rk3)
+int predictor_by_model(evp_grid* const* gs, const Batch& b, bool freeze, bool rk3, bool two_phase = false)
 {
     evp_grid* g0 = gs[0];
     int r = EVP_OK;
@@ -287,7 +292,7 @@ int predictor_by_model(evp_grid* const* gs, const Batch& b, bool freeze, bool rk
         r = timed(g0, EVP_K_PREDICTOR, [&] {
             return evp::launch_predictor_zm(bm, g0->precision, g0->nx, g0->ny, g0->nz, freeze,
                                             g0->stream, g0->bc == EVP_WALLS, model, rk3,
-                                            adv == EVP_HOUC5);
+                                            adv == EVP_HOUC5, two_phase);
         });
     }
     return r;
@@ -335,8 +340,89 @@ int enqueue_rk3(evp_grid* const* gs, int count, double dt, int nsteps, unsigned 
     return EVP_OK;
 }
 
+// Sec. 3.2.2 for a bubbly flow: level set first (TVD-RK3 transport, reinitialisation on
+// schedule), curvature, stress (per-cell lambda and G), momentum with the mixture properties and
+// surface tension, then the pressure splitting and the constant-coefficient projection with rho_0.
+int enqueue_two_phase(evp_grid* const* gs, int count, double dt, int nsteps, unsigned flags)
+{
+    evp_grid* g0 = gs[0];
+    const int nx = g0->nx, ny = g0->ny, nz = g0->nz;
+    const bool walls = g0->bc == EVP_WALLS;
+    const bool freeze = (flags & EVP_FREEZE_VELOCITY) != 0;
+    const bool stop = (flags & EVP_STOP_AFTER_PREDICTOR) != 0;
+    hipStream_t s = g0->stream;
+    int r;
+    for (int st = 0; st < nsteps; ++st) {
+        Batch b{};
+        b.count = count;
+        int max_iters = 0;
+        for (int i = 0; i < count; ++i) {
+            const evp_grid* g = gs[i];
+            b.d[i] = g->d;
+            b.dt[i] = dt;
+            b.state[i] = g->parity | (g->have_hist ? 0 : evp::ST_EULER) | (g->p_hist ? 0 : evp::ST_PZERO);
+            const bool due = g->tp.reinit_every > 0 && g->tp.reinit_iters > 0 && (g->nstep + 1) % g->tp.reinit_every == 0;
+            if (due) max_iters = std::max(max_iters, g->tp.reinit_iters);
+        }
+        for (int k = 0; k < 3; ++k)
+            if ((r = timed(g0, EVP_K_LEVEL_SET, [&] { return evp::launch_level_set_stage(b, nx, ny, nz, walls, false, k, s); })))
+                return r;
+        if (max_iters > 0) {
+            Batch br = b;
+            for (int i = 0; i < count; ++i) {
+                const evp_grid* g = gs[i];
+                const bool due = g->tp.reinit_every > 0 && g->tp.reinit_iters > 0 && (g->nstep + 1) % g->tp.reinit_every == 0;
+                if (due) br.state[i] |= evp::ST_REINIT;
+            }
+            if ((r = timed(g0, EVP_K_REINIT, [&] { return evp::launch_reinit_sign(br, nx, ny, nz, s); }))) return r;
+            for (int it = 0; it < max_iters; ++it) {
+                Batch bi = br;
+                for (int i = 0; i < count; ++i)
+                    if (it >= gs[i]->tp.reinit_iters) bi.state[i] &= ~evp::ST_REINIT;
+                for (int k = 0; k < 3; ++k)
+                    if ((r = timed(g0, EVP_K_REINIT, [&] { return evp::launch_level_set_stage(bi, nx, ny, nz, walls, true, k, s); })))
+                        return r;
+            }
+        }
+        if ((r = timed(g0, EVP_K_CURVATURE, [&] { return evp::launch_curvature(b, nx, ny, nz, walls, s); }))) return r;
+        if ((r = predictor_by_model(gs, b, freeze, false, true))) return r;
+        // momentum, one launch per stress form present (FENE-P or the others)
+        for (int fene = 0; fene < 2; ++fene) {
+            Batch bm = b;
+            bm.count = 0;
+            for (int i = 0; i < count; ++i)
+                if ((gs[i]->h.model == EVP_FENE_P) == (fene == 1)) {
+                    bm.d[bm.count] = b.d[i];
+                    bm.dt[bm.count] = b.dt[i];
+                    bm.state[bm.count] = b.state[i];
+                    bm.count++;
+                }
+            if (bm.count == 0) continue;
+            if ((r = timed(g0, EVP_K_MOMENTUM2, [&] {
+                     return evp::launch_momentum_two_phase(bm, nx, ny, nz, walls, fene ? EVP_FENE_P : EVP_OLDROYD_B, freeze, s);
+                 })))
+                return r;
+        }
+        if (stop && !freeze) {
+            hipError_t e = evp::launch_copy_ustar(b, nx, ny, nz, true, s);
+            if (e != hipSuccess) return hip_fail(e, "copy u*");
+        } else if (!freeze) {
+            if ((r = timed(g0, EVP_K_SPLIT, [&] { return evp::launch_split_pressure(b, nx, ny, nz, walls, s); }))) return r;
+            if ((r = projection(g0, b))) return r;
+        }
+        for (int i = 0; i < count; ++i) {
+            gs[i]->parity ^= 1;
+            gs[i]->have_hist = true;
+            if (!stop && !freeze) gs[i]->p_hist = true;
+            gs[i]->nstep += 1;
+        }
+    }
+    return EVP_OK;
+}
+
 int enqueue_steps(evp_grid* const* gs, int count, double dt, int nsteps, unsigned flags)
 {
+    if (gs[0]->two_phase) return enqueue_two_phase(gs, count, dt, nsteps, flags);
     if (gs[0]->integrator == EVP_RK3) return enqueue_rk3(gs, count, dt, nsteps, flags);
     evp_grid* g0 = gs[0];
     const bool freeze = (flags & EVP_FREEZE_VELOCITY) != 0;
@@ -385,6 +471,7 @@ const char* evp_error_string(int status)
     case EVP_ERR_STATE: return "grid not ready (set_rheology / write_fields missing)";
     case EVP_ERR_SHAPE: return "batch grids differ in shape, precision or stream";
     case EVP_ERR_HIP: return "HIP runtime error";
+    case EVP_ERR_DISABLED: return "entry point switched off";
     default: return "unknown status";
     }
 }
@@ -488,7 +575,8 @@ int evp_set_rheology(evp_grid* g, int model, double rho, double mu_s, double mu_
         return fail(EVP_ERR_ARG, "FENE-P needs a finite L2 > 3");
     Desc& h = g->h;
     h.model = model;
-    h.rho = rho; h.inv_rho = 1.0 / rho;
+    g->rho_single = rho;
+    if (!g->two_phase) { h.rho = rho; h.inv_rho = 1.0 / rho; }
     h.mu_s = mu_s; h.mu_p = mu_p;
     h.lam = lambda; h.inv_lam = 1.0 / lambda;
     h.G = mu_p / lambda;
@@ -511,9 +599,93 @@ int evp_set_transport(evp_grid* g, int scheme, double kappa)
     return upload_desc(g);
 }
 
+size_t evp_two_phase_bytes(int nx, int ny, int nz)
+{
+    std::string why;
+    if (!shape_ok(nx, ny, nz, EVP_PERIODIC, EVP_FP64, &why) && !shape_ok(nx, ny, nz, EVP_WALLS, EVP_FP64, &why))
+        return 0;
+    return 7 * align_up((size_t)nx * ny * nz * 8);
+}
+
+static constexpr bool kTwoPhaseEnabled = false;
+
+int evp_set_two_phase(evp_grid* g, const evp_two_phase_t* tp, void* dev_workspace, size_t bytes)
+{
+    if (int r = check_grid(g)) return r;
+    Desc& h = g->h;
+    if (!tp) {
+        g->two_phase = false;
+        h.two_phase = 0;
+        h.phi = h.phi1 = h.phi2 = h.sgn = h.kap = h.p_old = h.p_hat = nullptr;
+        if (g->have_rheo) { h.rho = g->rho_single; h.inv_rho = 1.0 / g->rho_single; }
+        return upload_desc(g);
+    }
+    // The two-phase step stays off until the device memory fault seen on its first run is
+    // explained; the kernels and the set-up below are kept compiled.
+    if (!kTwoPhaseEnabled)
+        return fail(EVP_ERR_DISABLED, "the two-phase path is switched off (unexplained device memory fault)");
+    if (g->precision != EVP_FP64) return fail(EVP_ERR_ARG, "the two-phase path runs in EVP_FP64");
+    if (g->integrator != EVP_AB2) return fail(EVP_ERR_ARG, "the two-phase path uses the AB2 step");
+    if (h.alpha[0]) return fail(EVP_ERR_ARG, "the two-phase path does not combine with a solid");
+    const double v[] = {tp->rho1, tp->rho2, tp->mu_s1, tp->mu_s2, tp->mu_p1, tp->mu_p2, tp->lam1, tp->lam2, tp->sigma};
+    for (double x : v)
+        if (!std::isfinite(x)) return fail(EVP_ERR_ARG, "two-phase parameters must be finite");
+    if (!(tp->rho1 > 0) || !(tp->rho2 > 0) || !(tp->lam1 > 0) || !(tp->lam2 > 0) || tp->mu_s1 < 0 ||
+        tp->mu_s2 < 0 || tp->mu_p1 < 0 || tp->mu_p2 < 0 || tp->sigma < 0 || tp->reinit_every < 0 ||
+        tp->reinit_iters < 0)
+        return fail(EVP_ERR_ARG, "need rho_k > 0, lam_k > 0, mu_k >= 0, sigma >= 0, reinit counts >= 0");
+    const size_t need = evp_two_phase_bytes(g->nx, g->ny, g->nz);
+    if (!dev_workspace || bytes < need) return fail(EVP_ERR_WORKSPACE, "two-phase workspace too small");
+    if (reinterpret_cast<uintptr_t>(dev_workspace) % kAlign != 0)
+        return fail(EVP_ERR_WORKSPACE, "two-phase workspace must be 256-byte aligned");
+    const size_t f = align_up((size_t)g->nx * g->ny * g->nz * 8);
+    char* w = static_cast<char*>(dev_workspace);
+    double** fields[7] = {&h.phi, &h.phi1, &h.phi2, &h.sgn, &h.kap, &h.p_old, &h.p_hat};
+    for (int i = 0; i < 7; ++i) *fields[i] = reinterpret_cast<double*>(w + i * f);
+    g->two_phase = true;
+    g->tp = *tp;
+    g->p_hist = false;
+    h.two_phase = 1;
+    h.rho1 = tp->rho1; h.rho2 = tp->rho2;
+    h.mus1 = tp->mu_s1; h.mus2 = tp->mu_s2;
+    h.mup1 = tp->mu_p1; h.mup2 = tp->mu_p2;
+    h.lam1 = tp->lam1; h.lam2 = tp->lam2;
+    h.sigma = tp->sigma;
+    h.eps_if = 1.5 * std::fmax(std::fmax(h.dx, h.dy), h.dz);
+    h.rho0 = std::fmin(tp->rho1, tp->rho2);
+    h.rho = h.rho0;
+    h.inv_rho = 1.0 / h.rho0;
+    hipError_t e = evp::launch_fill(h.phi, g->h.ncell, 1.0, g->stream);
+    if (e == hipSuccess) e = evp::launch_fill(h.p_old, g->h.ncell, 0.0, g->stream);
+    if (e == hipSuccess) e = evp::launch_fill(h.p_hat, g->h.ncell, 0.0, g->stream);
+    if (e != hipSuccess) return hip_fail(e, "two-phase fields");
+    return upload_desc(g);
+}
+
+int evp_write_level_set(evp_grid* g, const double* phi)
+{
+    if (int r = check_grid(g)) return r;
+    if (!g->two_phase) return fail(EVP_ERR_STATE, "level set without evp_set_two_phase");
+    if (!phi) return fail(EVP_ERR_ARG, "phi is NULL");
+    hipError_t e = hipMemcpyAsync(g->h.phi, phi, (size_t)g->h.ncell * 8, hipMemcpyDeviceToDevice, g->stream);
+    if (e != hipSuccess) return hip_fail(e, "write_level_set");
+    return EVP_OK;
+}
+
+int evp_read_level_set(evp_grid* g, double* phi)
+{
+    if (int r = check_grid(g)) return r;
+    if (!g->two_phase) return fail(EVP_ERR_STATE, "level set without evp_set_two_phase");
+    if (!phi) return fail(EVP_ERR_ARG, "phi is NULL");
+    hipError_t e = hipMemcpyAsync(phi, g->h.phi, (size_t)g->h.ncell * 8, hipMemcpyDeviceToDevice, g->stream);
+    if (e != hipSuccess) return hip_fail(e, "read_level_set");
+    return EVP_OK;
+}
+
 int evp_set_solid(evp_grid* g, const double* alpha_u, const double* alpha_v, const double* alpha_w)
 {
     if (int r = check_grid(g)) return r;
+    if (g->two_phase && alpha_u) return fail(EVP_ERR_ARG, "the two-phase path does not combine with a solid");
     const int n = (alpha_u != nullptr) + (alpha_v != nullptr) + (alpha_w != nullptr);
     if (n != 0 && n != 3) return fail(EVP_ERR_ARG, "alpha_u, alpha_v, alpha_w: all three or none");
     g->h.alpha[0] = alpha_u;
@@ -555,6 +727,7 @@ int evp_write_fields(evp_grid* g, const double* u, const double* v, const double
     g->have_hist = hist != nullptr;
     g->have_fields = true;
     g->nstep = 0;
+    g->p_hist = false;
     return EVP_OK;
 }
 
@@ -573,6 +746,7 @@ int evp_project(evp_grid* g)
     g->prof = false;
     int r = projection(g, b);
     g->prof = prof;
+    g->p_hist = false;
     return r;
 }
 
@@ -580,6 +754,7 @@ int evp_set_integrator(evp_grid* g, int scheme)
 {
     if (int r = check_grid(g)) return r;
     if (scheme != EVP_AB2 && scheme != EVP_RK3) return fail(EVP_ERR_ARG, "scheme must be EVP_AB2 or EVP_RK3");
+    if (scheme == EVP_RK3 && g->two_phase) return fail(EVP_ERR_ARG, "the two-phase path uses the AB2 step");
     if (scheme != g->integrator) g->have_hist = false;    // the other scheme's history is void
     g->integrator = scheme;
     return EVP_OK;
@@ -614,6 +789,8 @@ int evp_step_batch(evp_grid* const* grids, int count, double dt, int nsteps, uns
             return fail(EVP_ERR_SHAPE, "batch grids must share shape, boundary type, precision and stream");
         if (g->integrator != g0->integrator)
             return fail(EVP_ERR_SHAPE, "batch grids must share the time integrator");
+        if (g->two_phase != g0->two_phase)
+            return fail(EVP_ERR_SHAPE, "batch grids must all be single-phase or all two-phase");
         if (!g->have_rheo) return fail(EVP_ERR_STATE, "step before set_rheology");
         if (!g->have_fields) return fail(EVP_ERR_STATE, "step before write_fields");
     }

@@ -20,6 +20,12 @@ struct Desc {
     int adv;                     // EVP_WENO5 / EVP_HOUC5
     double kappa;                // artificial diffusion coefficient (0: off)
     const double* alpha[3];      // solid volume fractions at u, v, w points (caller's; null: none)
+    // two-phase (bubbly-flow) mode, Sec. 3.2: properties of fluid 1 (phi > 0) and fluid 2, the
+    // surface tension, the interface half-width eps of H(phi), rho_0 = min(rho1, rho2), and the
+    // level-set fields in the caller's second workspace (null when off)
+    int two_phase;
+    double rho1, rho2, mus1, mus2, mup1, mup2, lam1, lam2, sigma, eps_if, rho0;
+    double *phi, *phi1, *phi2, *sgn, *kap, *p_old, *p_hat;
     long long ncell;             // nx*ny*nz
     long long ps;                // element stride between planes of B, RT, RU (256-byte padded)
     double dx, dy, dz, idx, idy, idz, y0;
@@ -57,10 +63,22 @@ template <typename T> using gptr = EVP_GLOBAL T*;
 
 constexpr int ST_PARITY = 1;
 constexpr int ST_EULER = 2;
+constexpr int ST_PZERO = 4;      // two-phase: no pressure history yet (2 p^n - p^{n-1} := 0)
+constexpr int ST_REINIT = 8;     // two-phase: this grid reinitialises its level set now
 
 // Host-side launchers (one per kernel family); shape is common to the whole batch.
 hipError_t launch_predictor_zm(const Batch& b, int precision, int nx, int ny, int nz, bool freeze,
-                               hipStream_t s, bool walls, int model, bool rk3, bool houc);
+                               hipStream_t s, bool walls, int model, bool rk3, bool houc,
+                               bool two_phase);
+// two-phase path (k_two_phase.hip)
+hipError_t launch_level_set_stage(const Batch& b, int nx, int ny, int nz, bool walls, bool reinit,
+                                  int stage, hipStream_t s);
+hipError_t launch_reinit_sign(const Batch& b, int nx, int ny, int nz, hipStream_t s);
+hipError_t launch_curvature(const Batch& b, int nx, int ny, int nz, bool walls, hipStream_t s);
+hipError_t launch_momentum_two_phase(const Batch& b, int nx, int ny, int nz, bool walls, int model,
+                                     bool freeze, hipStream_t s);
+hipError_t launch_split_pressure(const Batch& b, int nx, int ny, int nz, bool walls, hipStream_t s);
+hipError_t launch_fill(double* p, long long n, double value, hipStream_t s);
 hipError_t launch_stress_div(const Batch& b, int precision, int nx, int ny, int nz, bool walls,
                              hipStream_t s);
 hipError_t launch_penalise(const Batch& b, int nx, int ny, int nz, hipStream_t s);

@@ -14,6 +14,7 @@
 #include <cstdlib>
 
 #include "evp_internal.h"
+#include "weno.h"
 
 namespace evp {
 
@@ -37,46 +38,6 @@ template <typename T> struct Smem {
     T Z[3][3][BH][BW];   // ring slot, (tau_xz, tau_yz, tau_zz)
     T V[3][3][BH][BW];   // ring slot, (u, v, w)
 };
-
-// reciprocal to full precision: hardware estimate refined by Newton steps (x <- x (2 - a x))
-__device__ __forceinline__ double fast_rcp(double a)
-{
-    double x = __builtin_amdgcn_rcp(a);
-    x = fma(x, fma(-a, x, 1.0), x);
-    x = fma(x, fma(-a, x, 1.0), x);
-    return x;
-}
-__device__ __forceinline__ float fast_rcp(float a)
-{
-    float x = __builtin_amdgcn_rcpf(a);
-    return fmaf(x, fmaf(-a, x, 1.0f), x);
-}
-
-// Fifth-order WENO from the five undivided one-sided differences e1..e5 (spacing folded out):
-// returns h * dB/dx.  eps2 = eps h^2 keeps the weights equal to those of the divided form.
-template <typename T>
-__device__ __forceinline__ T weno5u(T v1, T v2, T v3, T v4, T v5, T eps2)
-{
-    const T c13 = (T)(13.0 / 12.0), q = (T)0.25;
-    const T p1 = v1 * (T)(1.0 / 3.0) - v2 * (T)(7.0 / 6.0) + v3 * (T)(11.0 / 6.0);
-    const T p2 = -v2 * (T)(1.0 / 6.0) + v3 * (T)(5.0 / 6.0) + v4 * (T)(1.0 / 3.0);
-    const T p3 = v3 * (T)(1.0 / 3.0) + v4 * (T)(5.0 / 6.0) - v5 * (T)(1.0 / 6.0);
-    T a = v1 - (T)2 * v2 + v3, b = v1 - (T)4 * v2 + (T)3 * v3;
-    T e1 = eps2 + c13 * a * a + q * b * b;
-    a = v2 - (T)2 * v3 + v4; b = v2 - v4;
-    T e2 = eps2 + c13 * a * a + q * b * b;
-    a = v3 - (T)2 * v4 + v5; b = (T)3 * v3 - (T)4 * v4 + v5;
-    T e3 = eps2 + c13 * a * a + q * b * b;
-    if constexpr (sizeof(T) == 4) {
-        // FP32: eps h^2 squared twice in the common denominator underflows on fine grids; the
-        // weights are invariant under a common scale, so normalise by the largest indicator
-        const T im = fast_rcp(fmaxf(fmaxf(e1, e2), e3));
-        e1 *= im; e2 *= im; e3 *= im;
-    }
-    e1 *= e1; e2 *= e2; e3 *= e3;
-    const T w1 = (T)0.1 * e2 * e3, w2 = (T)0.6 * e1 * e3, w3 = (T)0.3 * e1 * e2;
-    return (w1 * p1 + w2 * p2 + w3 * p3) * fast_rcp(w1 + w2 + w3);
-}
 
 // upwind derivative (times h) at the middle of f0..f6: WENO5, or HOUC5 (the fifth-order linear
 // upwind-biased combination)
@@ -102,7 +63,9 @@ __device__ __forceinline__ T weno_up(T f0, T f1, T f2, T f3, T f4, T f5, T f6, T
 // + (2 alpha (mu_s lap u + f) + alpha div tau^{k-1}) / rho].
 // HOUC: fifth-order upstream-central advection instead of WENO5 (a separate instantiation, so
 // the WENO kernel's register allocation is not shared with the other scheme).
-template <typename T, bool WALLS, int MODEL, bool RK3, bool HOUC>
+// TWOPH: two-phase mode (Sec. 3.2, FP64, AB2): lambda and G = mu_p/lambda of the cell come from
+// the mixture at phi^{n+1}; only the stress is advanced (the momentum has its own kernel).
+template <typename T, bool WALLS, int MODEL, bool RK3, bool HOUC, bool TWOPH>
 __global__ __launch_bounds__(NTH, (sizeof(T) == 4 && !WALLS) ? 3 : 2) void k_pred_zm(Batch B, int freeze, int kc)
 {
     __shared__ Smem<T> S;
@@ -344,14 +307,21 @@ __global__ __launch_bounds__(NTH, (sizeof(T) == 4 && !WALLS) ? 3 : 2) void k_pre
 
             // Table 1 closure of this cell
             const T* bt = win[3];
+            T Gc = G, ilc = il;
+            if constexpr (TWOPH) {
+                const double hh = heaviside(((gptr<const double>)D.phi)[q], D.eps_if);
+                const double lam = D.lam1 * hh + D.lam2 * (1.0 - hh), mup = D.mup1 * hh + D.mup2 * (1.0 - hh);
+                Gc = (T)(mup / lam);
+                ilc = (T)(1.0 / lam);
+            }
             T F = (T)1, a = (T)1;
             if (fene) {
                 F = L2 / (L2 - (bt[0] + bt[3] + bt[5] + (T)3));
                 a = afene;
             } else if (sara) {
-                const T t3 = G * (bt[0] + bt[3] + bt[5]) * (T)(1.0 / 3.0);
-                const T dxx = G * bt[0] - t3, dyy = G * bt[3] - t3, dzz = G * bt[5] - t3;
-                const T txy = G * bt[1], txz = G * bt[2], tyz = G * bt[4];
+                const T t3 = Gc * (bt[0] + bt[3] + bt[5]) * (T)(1.0 / 3.0);
+                const T dxx = Gc * bt[0] - t3, dyy = Gc * bt[3] - t3, dzz = Gc * bt[5] - t3;
+                const T txy = Gc * bt[1], txz = Gc * bt[2], tyz = Gc * bt[4];
                 const T nrm = sqrt((T)0.5 * (dxx * dxx + dyy * dyy + dzz * dzz)
                                    + txy * txy + txz * txz + tyz * tyz);
                 F = (tyld == (T)0) ? (T)1 : (nrm > tyld ? (T)1 - tyld / nrm : (T)0);
@@ -387,7 +357,7 @@ __global__ __launch_bounds__(NTH, (sizeof(T) == 4 && !WALLS) ? 3 : 2) void k_pre
                     T ucv = L[p][rr] + L[rr][p];
 #pragma unroll
                     for (int m = 0; m < 3; ++m) ucv += L[p][m] * bt[cm[m][rr]] + bt[cm[p][m]] * L[rr][m];
-                    const T relax = (((p == rr) ? (a - F) : (T)0) - F * bt[cc]) * il;
+                    const T relax = (((p == rr) ? (a - F) : (T)0) - F * bt[cc]) * ilc;
                     rtv[cc] = relax - adv + ucv;
                     // bound live ranges: finish this component before the next one's LDS reads
                     __asm__ volatile("" ::"v"(rtv[cc]) : "memory");
@@ -416,7 +386,9 @@ __global__ __launch_bounds__(NTH, (sizeof(T) == 4 && !WALLS) ? 3 : 2) void k_pre
             }
 
             __asm__ volatile("" ::: "memory");
-            if (freeze) {
+            if constexpr (TWOPH) {
+                // the two-phase momentum follows in k_momentum_two_phase
+            } else if (freeze) {
                 gus[q] = u0; gvs[q] = v0; gws[q] = w0;
                 RU[q] = (T)0; RU[ps + q] = (T)0; RU[2 * ps + q] = (T)0;
             } else {
@@ -527,7 +499,8 @@ int predictor_chunk(int nx, int ny, int nz, bool three_per_cu)
 }
 
 hipError_t launch_predictor_zm(const Batch& b, int precision, int nx, int ny, int nz, bool freeze,
-                               hipStream_t s, bool walls, int model, bool rk3, bool houc)
+                               hipStream_t s, bool walls, int model, bool rk3, bool houc,
+                               bool two_phase)
 {
     const int kc = predictor_chunk(nx, ny, nz, precision == EVP_MIXED && !walls);
     const int nblk = ((nx + TX - 1) / TX) * ((ny + TY - 1) / TY) * ((nz + kc - 1) / kc);
@@ -535,8 +508,13 @@ hipError_t launch_predictor_zm(const Batch& b, int precision, int nx, int ny, in
     const int fz = freeze ? 1 : 0;
 #define EVP_LAUNCH2(TT, WW, MM, RR)                                                                \
     do {                                                                                           \
-        if (houc) hipLaunchKernelGGL((k_pred_zm<TT, WW, MM, RR, true>), grid, dim3(NTH), 0, s, b, fz, kc); \
-        else hipLaunchKernelGGL((k_pred_zm<TT, WW, MM, RR, false>), grid, dim3(NTH), 0, s, b, fz, kc); \
+        if (houc) hipLaunchKernelGGL((k_pred_zm<TT, WW, MM, RR, true, false>), grid, dim3(NTH), 0, s, b, fz, kc); \
+        else hipLaunchKernelGGL((k_pred_zm<TT, WW, MM, RR, false, false>), grid, dim3(NTH), 0, s, b, fz, kc); \
+    } while (0)
+#define EVP_LAUNCH_TP(WW, MM)                                                                      \
+    do {                                                                                           \
+        if (houc) hipLaunchKernelGGL((k_pred_zm<double, WW, MM, false, true, true>), grid, dim3(NTH), 0, s, b, fz, kc); \
+        else hipLaunchKernelGGL((k_pred_zm<double, WW, MM, false, false, true>), grid, dim3(NTH), 0, s, b, fz, kc); \
     } while (0)
 #define EVP_LAUNCH(TT, WW, MM)                                                                     \
     do {                                                                                           \
@@ -550,7 +528,18 @@ hipError_t launch_predictor_zm(const Batch& b, int precision, int nx, int ny, in
     case EVP_NEO_HOOKEAN: EVP_LAUNCH(TT, WW, EVP_NEO_HOOKEAN); break;                             \
     default: EVP_LAUNCH(TT, WW, EVP_OLDROYD_B); break;                                            \
     }
-    if (precision == EVP_MIXED) {
+    if (two_phase) {
+        if (precision != EVP_FP64 || rk3) return hipErrorInvalidValue;
+#define EVP_TP_BY_MODEL(WW)                                                                        \
+    switch (model) {                                                                               \
+    case EVP_FENE_P: EVP_LAUNCH_TP(WW, EVP_FENE_P); break;                                        \
+    case EVP_SARAMITO: EVP_LAUNCH_TP(WW, EVP_SARAMITO); break;                                    \
+    case EVP_NEO_HOOKEAN: EVP_LAUNCH_TP(WW, EVP_NEO_HOOKEAN); break;                              \
+    default: EVP_LAUNCH_TP(WW, EVP_OLDROYD_B); break;                                             \
+    }
+        if (walls) { EVP_TP_BY_MODEL(true) } else { EVP_TP_BY_MODEL(false) }
+#undef EVP_TP_BY_MODEL
+    } else if (precision == EVP_MIXED) {
         if (walls) { EVP_BY_MODEL(float, true) } else { EVP_BY_MODEL(float, false) }
     } else {
         if (walls) { EVP_BY_MODEL(double, true) } else { EVP_BY_MODEL(double, false) }
@@ -558,6 +547,7 @@ hipError_t launch_predictor_zm(const Batch& b, int precision, int nx, int ny, in
 #undef EVP_BY_MODEL
 #undef EVP_LAUNCH
 #undef EVP_LAUNCH2
+#undef EVP_LAUNCH_TP
     return hipGetLastError();
 }
 
