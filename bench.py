@@ -33,6 +33,10 @@ STRESS_DIV_BYTES = {"fp64": 6 * 8 + 48, "mixed": 6 * 4 + 48}
 
 
 TRAFFIC_FILE = os.path.join(HERE, "profiles", "predictor_kolmogorov128_hbm_traffic.txt")
+COUNTER_FILE = os.path.join(HERE, "profiles", "predictor_kolmogorov128_sq_counters.txt")
+RHEOLOGY_TEXT = {"kolmogorov128": "Saramito Wi=1 Bi=0.5 beta=0.5 Re=1000",
+                 "channel_fene_p": "FENE-P L^2=900 Wi=5 beta=0.9 Re=2000",
+                 "channel_saramito": "Saramito Wi=2 Bi=0.2 beta=0.1 Re=5000"}
 PRED_SOURCE = os.path.join(HERE, "paper_1803_09563_amd", "csrc", "k_predictor_zm.hip")
 
 
@@ -53,6 +57,23 @@ def measured_traffic(precision="double"):
     return int(t.group(1))
 
 
+def measured_valu_busy():
+    """Fraction of SIMD cycles the FP64 predictor keeps the vector ALU busy, from the committed
+    rocprofv3 SQ-counter summary, or None if the kernel source changed since it was taken."""
+    import hashlib
+    import re
+    try:
+        text = open(COUNTER_FILE).read()
+        sha = hashlib.sha256(open(PRED_SOURCE, "rb").read()).hexdigest()[:16]
+    except OSError:
+        return None
+    m = re.search(r"sha256\[:16\] = ([0-9a-f]{16})", text)
+    t = re.search(r"valu_busy_double = ([0-9.]+)", text)
+    if not m or not t or m.group(1) != sha:
+        return None
+    return float(t.group(1))
+
+
 def _args():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -66,6 +87,10 @@ def _args():
     ap.add_argument("--no-rk3", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=500)
+    ap.add_argument("--no-channel", action="store_true")
+    ap.add_argument("--workload", default="kolmogorov128",
+                    choices=("kolmogorov128", "channel_fene_p", "channel_saramito"),
+                    help="main workload (the channel ones are for profiling runs)")
     ap.add_argument("--quiet", action="store_true")
     return ap.parse_args()
 
@@ -161,7 +186,7 @@ def cpu_baseline(wl, steps, quiet):
     _log(f"cpu oracle: {steps} steps in {el:.2f} s on {threads} threads", quiet)
     return {"value": wl.ncell * steps / el, "unit": "cell-steps/s", "cores": threads,
             "kind": "oracle",
-            "sample": f"{steps} FP64 steps of the same {wl.nx}^3 workload after 1 warm-up step "
+            "sample": f"{steps} FP64 steps of the same {wl.nx}x{wl.ny}x{wl.nz} workload after 1 warm-up step "
                       f"(C predictor on {threads} OpenMP threads + numpy FFT projection), "
                       f"{el:.1f} s"}
 
@@ -175,7 +200,9 @@ def main():
     import torch
     from paper_1803_09563_amd import inputs
 
-    wl = inputs.kolmogorov_saramito(a.n)
+    wl = {"kolmogorov128": lambda: inputs.kolmogorov_saramito(a.n),
+          "channel_fene_p": inputs.channel_fene_p,
+          "channel_saramito": inputs.channel_saramito}[a.workload]()
     res = {"fp64": run_gpu(wl, "fp64", a.steps, a.warmup, a.quiet)}
     if not a.no_mixed:
         res["mixed"] = run_gpu(wl, "mixed", a.steps, a.warmup, a.quiet)
@@ -206,12 +233,16 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic (seeded Kolmogorov-forced Saramito flow)",
-        "config": {"workload": wl.name, "grid": f"{wl.nx}x{wl.ny}x{wl.nz} periodic",
-                   "rheology": "Saramito Wi=1 Bi=0.5 beta=0.5 Re=1000", "dt": wl.dt,
+        "config": {"workload": wl.name,
+                   "grid": f"{wl.nx}x{wl.ny}x{wl.nz} " + ("channel" if wl.walls else "periodic"),
+                   "rheology": RHEOLOGY_TEXT.get(a.workload, ""), "dt": wl.dt,
                    "precision": "fp64"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic("double") if a.n == 128 else None,
+                     "traffic": (measured_traffic("double")
+                                 if a.n == 128 and a.workload == "kolmogorov128" else None),
+                     "valu_busy": (measured_valu_busy()
+                                   if a.n == 128 and a.workload == "kolmogorov128" else None),
                      "kernel": "predictor (fused stress + momentum stencil)",
                      "bytes_per_cell": PRED_BYTES["fp64"], "avg_launch_us": pred_ms * 1e3},
         "step_hbm_frac": STEP_BYTES["fp64"] * value / 1e9 / HBM_PEAK_GBS,
@@ -250,6 +281,25 @@ def main():
             out["variants"][name] = {"value": wl.ncell * n_v / (r["ms"] * 1e-3),
                                      "unit": "cell-steps/s", "steps": n_v,
                                      "predictor_avg_us": pk_v["ms"] / max(pk_v["launches"], 1) * 1e3}
+    if not a.no_channel and a.workload == "kolmogorov128":
+        # the channel workloads (periodic x and z, no-slip walls in y: FFT in x and z, tridiagonal
+        # solve in y), FENE-P 256x128x128 in the mixed form and Saramito 512x256x256 in both forms
+        out["channel"] = {}
+        for wl_c, precs in ((inputs.channel_fene_p(), ("mixed",)),
+                            (inputs.channel_saramito(), ("fp64", "mixed"))):
+            d = {"workload": wl_c.name, "cells": wl_c.ncell}
+            n_c = wl_c.steps if a.steps == 200 else a.steps
+            for prec in precs:
+                r = run_gpu(wl_c, prec, n_c, a.warmup, a.quiet)
+                pk_c = r["prof"]["predictor"]
+                pc_ms = pk_c["ms"] / max(pk_c["launches"], 1)
+                d[prec] = {"value": wl_c.ncell * n_c / (r["ms"] * 1e-3), "unit": "cell-steps/s",
+                           "steps": n_c, "ms_per_step": r["ms"] / n_c,
+                           "predictor_hbm_frac": PRED_BYTES[prec] * wl_c.ncell / (pc_ms * 1e-3)
+                           / 1e9 / HBM_PEAK_GBS,
+                           "kernel_avg_us": {k: round(v["ms"] / max(v["launches"], 1) * 1e3, 2)
+                                             for k, v in r["prof"].items() if v["launches"]}}
+            out["channel"][wl_c.name] = d
     if not a.no_serving:
         out["serving"] = serving(a.serving_requests, a.quiet)
     if not a.no_cpu_baseline:
