@@ -130,6 +130,8 @@ struct evp_grid {
     std::vector<hipEvent_t> free_events;
     long long prof_launches[EVP_K_COUNT];
     double prof_ms[EVP_K_COUNT];
+    evp::Side side;               // channel grids: second stream for the wall rows of the predictor
+    bool side_ready;
 };
 
 namespace {
@@ -273,6 +275,26 @@ constexpr double kRkXi[3] = {0.0, -17.0 / 60.0, -5.0 / 12.0};
 // The predictor is specialised per constitutive model and advection scheme: one launch per
 // (model, scheme) pair present in the batch, so a grid's arithmetic is the same alone and in any
 // batch.
+// the side stream of a channel grid, created on first use (default priority); nullptr if it
+// cannot be created, in which case the wall rows run after the interior on the main stream
+const evp::Side* side_of(evp_grid* g)
+{
+    if (g->bc != EVP_WALLS) return nullptr;
+    if (!g->side_ready) {
+        evp::Side sd{nullptr, nullptr, nullptr};
+        if (hipStreamCreateWithFlags(&sd.s, hipStreamNonBlocking) != hipSuccess) return nullptr;
+        if (hipEventCreateWithFlags(&sd.fork, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&sd.join, hipEventDisableTiming) != hipSuccess) {
+            if (sd.fork) (void)hipEventDestroy(sd.fork);
+            (void)hipStreamDestroy(sd.s);
+            return nullptr;
+        }
+        g->side = sd;
+        g->side_ready = true;
+    }
+    return &g->side;
+}
+
 int predictor_by_model(evp_grid* const* gs, const Batch& b, bool freeze, bool rk3, bool two_phase = false)
 {
     evp_grid* g0 = gs[0];
@@ -292,7 +314,7 @@ int predictor_by_model(evp_grid* const* gs, const Batch& b, bool freeze, bool rk
         r = timed(g0, EVP_K_PREDICTOR, [&] {
             return evp::launch_predictor_zm(bm, g0->precision, g0->nx, g0->ny, g0->nz, freeze,
                                             g0->stream, g0->bc == EVP_WALLS, model, rk3,
-                                            adv == EVP_HOUC5, two_phase);
+                                            adv == EVP_HOUC5, two_phase, side_of(g0));
         });
     }
     return r;
@@ -940,6 +962,12 @@ int evp_destroy_grid(evp_grid* g)
         fold_events(g);
     }
     for (hipEvent_t e : g->free_events) (void)hipEventDestroy(e);
+    if (g->side_ready) {
+        (void)hipStreamSynchronize(g->side.s);
+        (void)hipEventDestroy(g->side.fork);
+        (void)hipEventDestroy(g->side.join);
+        (void)hipStreamDestroy(g->side.s);
+    }
     delete g;
     return EVP_OK;
 }

@@ -67,9 +67,12 @@ constexpr int ST_PZERO = 4;      // two-phase: no pressure history yet (2 p^n - 
 constexpr int ST_REINIT = 8;     // two-phase: this grid reinitialises its level set now
 
 // Host-side launchers (one per kernel family); shape is common to the whole batch.
+// A second stream with a fork and a join event: work launched there runs beside the main
+// stream's and is joined back before the main stream goes on.
+struct Side { hipStream_t s; hipEvent_t fork, join; };
 hipError_t launch_predictor_zm(const Batch& b, int precision, int nx, int ny, int nz, bool freeze,
                                hipStream_t s, bool walls, int model, bool rk3, bool houc,
-                               bool two_phase);
+                               bool two_phase, const Side* side = nullptr);
 // two-phase path (k_two_phase.hip)
 hipError_t launch_level_set_stage(const Batch& b, int nx, int ny, int nz, bool walls, bool reinit,
                                   int stage, hipStream_t s);

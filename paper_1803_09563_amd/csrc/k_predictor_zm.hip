@@ -25,6 +25,11 @@ constexpr int RW = TX + 6, RH = TY + 6;    // B plane with a 3-cell halo
 constexpr int BW = TX + 2, BH = TY + 2;    // 1-cell halo box
 constexpr int BOX = BW * BH;
 
+// The tile rows (in y) one launch covers: rows.first + r for r < rows.count, shifted up by
+// rows.skip once they reach rows.skip_from (so one launch can take the bottom and top rows of a
+// channel and leave out the interior ones).
+struct Rows { int first, count, skip_from, skip; };
+
 __device__ __forceinline__ int modp(int i, int n)
 {
     int r = i % n;
@@ -66,7 +71,7 @@ __device__ __forceinline__ T weno_up(T f0, T f1, T f2, T f3, T f4, T f5, T f6, T
 // TWOPH: two-phase mode (Sec. 3.2, FP64, AB2): lambda and G = mu_p/lambda of the cell come from
 // the mixture at phi^{n+1}; only the stress is advanced (the momentum has its own kernel).
 template <typename T, bool WALLS, int MODEL, bool RK3, bool HOUC, bool TWOPH>
-__global__ __launch_bounds__(NTH, (sizeof(T) == 4 && !WALLS) ? 3 : 2) void k_pred_zm(Batch B, int freeze, int kc)
+__global__ __launch_bounds__(NTH, (sizeof(T) == 4 && !WALLS) ? 3 : 2) void k_pred_zm(Batch B, int freeze, int kc, Rows rows)
 {
     __shared__ Smem<T> S;
     const int b = blockIdx.y;
@@ -74,11 +79,13 @@ __global__ __launch_bounds__(NTH, (sizeof(T) == 4 && !WALLS) ? 3 : 2) void k_pre
     const int nx = D.nx, ny = D.ny, nz = D.nz;
     const int sxy = nx * ny;
     const int ps = (int)D.ps;
-    const int ntx = (nx + TX - 1) / TX, nty = (ny + TY - 1) / TY, nch = (nz + kc - 1) / kc;
+    const int ntx = (nx + TX - 1) / TX, nty = rows.count, nch = (nz + kc - 1) / kc;
     const int nblk = ntx * nty * nch;
     int bid = blockIdx.x;
     if ((nblk & 7) == 0) bid = (bid & 7) * (nblk >> 3) + (bid >> 3);     // XCD-contiguous tiles
-    const int tile_x = bid % ntx, tile_y = (bid / ntx) % nty, ch = bid / (ntx * nty);
+    const int tile_x = bid % ntx, ch = bid / (ntx * nty);
+    int tile_y = rows.first + (bid / ntx) % nty;
+    if (tile_y >= rows.skip_from) tile_y += rows.skip;
     const int i0 = tile_x * TX, j0 = tile_y * TY, k0 = ch * kc;
     const int k1 = min(k0 + kc, nz);
     const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
@@ -485,36 +492,69 @@ __global__ __launch_bounds__(NTH, (sizeof(T) == 4 && !WALLS) ? 3 : 2) void k_pre
 
 // planes per block: about as many blocks as can be resident (two per CU; three for the FP32
 // periodic kernel, whose registers allow three waves per SIMD), at least 4 planes per block
-int predictor_chunk(int nx, int ny, int nz, bool three_per_cu)
+int predictor_chunk_tiles(int tiles, int nz, bool three_per_cu)
 {
     static const int target_env = [] {
         const char* e = std::getenv("EVP_PRED_BLOCKS");
         return e ? std::atoi(e) : 0;
     }();
     const int target = target_env > 0 ? target_env : (three_per_cu ? 768 : 512);
-    const int tiles = ((nx + TX - 1) / TX) * ((ny + TY - 1) / TY);
     int nch = (target + tiles - 1) / tiles;
     nch = max(1, min(nch, nz / 4));
     return (nz + nch - 1) / nch;
 }
 
+int predictor_chunk(int nx, int ny, int nz, bool three_per_cu)
+{
+    return predictor_chunk_tiles(((nx + TX - 1) / TX) * ((ny + TY - 1) / TY), nz, three_per_cu);
+}
+
 hipError_t launch_predictor_zm(const Batch& b, int precision, int nx, int ny, int nz, bool freeze,
                                hipStream_t s, bool walls, int model, bool rk3, bool houc,
-                               bool two_phase)
+                               bool two_phase, const Side* side)
 {
-    const int kc = predictor_chunk(nx, ny, nz, precision == EVP_MIXED && !walls);
-    const int nblk = ((nx + TX - 1) / TX) * ((ny + TY - 1) / TY) * ((nz + kc - 1) / kc);
-    dim3 grid(nblk, b.count);
+    const int ntx = (nx + TX - 1) / TX, nty = (ny + TY - 1) / TY;
+    // Channel: tile rows whose whole stencil (B rows j0-3 .. j0+TY+2, velocity rows j0-1 ..
+    // j0+TY) lies in rows 0 .. ny-3 never see a ghost row or the top wall face; they run the
+    // periodic instantiation (same arithmetic there, and no spills of the ghost-row state), the
+    // rows next to the walls the wall instantiation.
+    int in_lo = 1, in_hi = walls ? (ny - 3) / TY : 0;
+    if (in_hi <= in_lo) in_lo = in_hi = 0;
     const int fz = freeze ? 1 : 0;
+    struct Part { bool w; Rows rows; };
+    Part parts[2];
+    int np = 0;
+    if (!walls) parts[np++] = {false, {0, nty, 1 << 30, 0}};
+    else {
+        if (in_hi > in_lo) parts[np++] = {false, {in_lo, in_hi - in_lo, 1 << 30, 0}};
+        if (in_hi > in_lo) parts[np++] = {true, {0, nty - (in_hi - in_lo), in_lo, in_hi - in_lo}};
+        else parts[np++] = {true, {0, nty, 1 << 30, 0}};
+    }
+    // The rows next to the walls run beside the interior on the side stream in the mixed form
+    // (measured faster for 256x128x128 and 512x256x256 channels); the FP64 wall kernel, which
+    // keeps more state per thread, competes worse for the CUs and runs after the interior.
+    const bool fork = np == 2 && side != nullptr && precision == EVP_MIXED;
+    if (fork) {
+        hipError_t e = hipEventRecord(side->fork, s);
+        if (e == hipSuccess) e = hipStreamWaitEvent(side->s, side->fork, 0);
+        if (e != hipSuccess) return e;
+    }
+    for (int ip = 0; ip < np; ++ip) {
+    const bool pw = parts[ip].w;
+    const Rows rows = parts[ip].rows;
+    const hipStream_t ls = (fork && pw) ? side->s : s;
+    const int kc = predictor_chunk_tiles(ntx * rows.count, nz, precision == EVP_MIXED && !pw);
+    const int nblk = ntx * rows.count * ((nz + kc - 1) / kc);
+    dim3 grid(nblk, b.count);
 #define EVP_LAUNCH2(TT, WW, MM, RR)                                                                \
     do {                                                                                           \
-        if (houc) hipLaunchKernelGGL((k_pred_zm<TT, WW, MM, RR, true, false>), grid, dim3(NTH), 0, s, b, fz, kc); \
-        else hipLaunchKernelGGL((k_pred_zm<TT, WW, MM, RR, false, false>), grid, dim3(NTH), 0, s, b, fz, kc); \
+        if (houc) hipLaunchKernelGGL((k_pred_zm<TT, WW, MM, RR, true, false>), grid, dim3(NTH), 0, ls, b, fz, kc, rows); \
+        else hipLaunchKernelGGL((k_pred_zm<TT, WW, MM, RR, false, false>), grid, dim3(NTH), 0, ls, b, fz, kc, rows); \
     } while (0)
 #define EVP_LAUNCH_TP(WW, MM)                                                                      \
     do {                                                                                           \
-        if (houc) hipLaunchKernelGGL((k_pred_zm<double, WW, MM, false, true, true>), grid, dim3(NTH), 0, s, b, fz, kc); \
-        else hipLaunchKernelGGL((k_pred_zm<double, WW, MM, false, false, true>), grid, dim3(NTH), 0, s, b, fz, kc); \
+        if (houc) hipLaunchKernelGGL((k_pred_zm<double, WW, MM, false, true, true>), grid, dim3(NTH), 0, ls, b, fz, kc, rows); \
+        else hipLaunchKernelGGL((k_pred_zm<double, WW, MM, false, false, true>), grid, dim3(NTH), 0, ls, b, fz, kc, rows); \
     } while (0)
 #define EVP_LAUNCH(TT, WW, MM)                                                                     \
     do {                                                                                           \
@@ -537,12 +577,18 @@ hipError_t launch_predictor_zm(const Batch& b, int precision, int nx, int ny, in
     case EVP_NEO_HOOKEAN: EVP_LAUNCH_TP(WW, EVP_NEO_HOOKEAN); break;                              \
     default: EVP_LAUNCH_TP(WW, EVP_OLDROYD_B); break;                                             \
     }
-        if (walls) { EVP_TP_BY_MODEL(true) } else { EVP_TP_BY_MODEL(false) }
+        if (pw) { EVP_TP_BY_MODEL(true) } else { EVP_TP_BY_MODEL(false) }
 #undef EVP_TP_BY_MODEL
     } else if (precision == EVP_MIXED) {
-        if (walls) { EVP_BY_MODEL(float, true) } else { EVP_BY_MODEL(float, false) }
+        if (pw) { EVP_BY_MODEL(float, true) } else { EVP_BY_MODEL(float, false) }
     } else {
-        if (walls) { EVP_BY_MODEL(double, true) } else { EVP_BY_MODEL(double, false) }
+        if (pw) { EVP_BY_MODEL(double, true) } else { EVP_BY_MODEL(double, false) }
+    }
+    }
+    if (fork) {
+        hipError_t e = hipEventRecord(side->join, side->s);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, side->join, 0);
+        if (e != hipSuccess) return e;
     }
 #undef EVP_BY_MODEL
 #undef EVP_LAUNCH
