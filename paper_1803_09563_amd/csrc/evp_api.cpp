@@ -47,7 +47,7 @@ bool is_23_smooth(int n)
 
 struct Layout {
     size_t desc, u, v, w, us, vs, ws, p, B0, B1, RT, RU, spec, twx, twy, twz, eigx, eigy, eigz,
-        piv, red, total;
+        piv, red, gauge, total;
     long long ps;
 };
 
@@ -97,6 +97,7 @@ Layout make_layout(int nx, int ny, int nz, int bc_y, int precision)
     L.eigx = take(nh * 8); L.eigy = take((size_t)ny * 8); L.eigz = take((size_t)nz * 8);
     L.piv = take(bc_y == EVP_WALLS ? ((size_t)nz / 2 + 1) * ny * nh * 8 : 8);
     L.red = take(kRedDoubles * 8);
+    L.gauge = take(8);
     L.total = off;
     return L;
 }
@@ -560,6 +561,7 @@ int evp_create_grid(int nx, int ny, int nz, double lx, double ly, double lz, int
     h.eigx = (const double*)(w + L.eigx); h.eigy = (const double*)(w + L.eigy); h.eigz = (const double*)(w + L.eigz);
     h.piv = (const double*)(w + L.piv);
     h.red = (double*)(w + L.red);
+    h.gauge = (double*)(w + L.gauge);
     g->d = (Desc*)(w + L.desc);
     g->parity = 0;
 

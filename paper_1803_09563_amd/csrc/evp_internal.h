@@ -43,6 +43,7 @@ struct Desc {
     const double *eigx, *eigy, *eigz;      // -(4/h^2) sin^2(pi k / N) per direction
     const double* piv;           // walls: Thomas pivots 1/(b_j - a c'_{j-1}) [nz/2+1][ny][nh]
     double* red;                 // reduction partials (health)
+    double* gauge;               // walls: volume mean of p before the zero-mean gauge (one value)
 };
 
 // Argument block of every batched kernel (by value; < 1 KiB).

@@ -271,8 +271,10 @@ __global__ __launch_bounds__(TH_NT) void k_thomas(Batch B)
 #pragma unroll
         for (int m = 0; m < TH_P; ++m) { r[m] = rn[m]; iv[m] = ivn[m]; }
     }
-    // backward sweep x_j = d'_j - c'_j x_{j+1}, c'_j = a / (b_j - a c'_{j-1})
+    // backward sweep x_j = d'_j - c'_j x_{j+1}, c'_j = a / (b_j - a c'_{j-1}); the (0, 0) mode
+    // also sums its profile for the zero-mean gauge
     double2 x = dp;
+    double sum = dp.x;
     auto bload = [&](int j1, double2* dd, double* cc) {
 #pragma unroll
         for (int m = 0; m < TH_P; ++m) {
@@ -289,21 +291,15 @@ __global__ __launch_bounds__(TH_NT) void k_thomas(Batch B)
             if (j1 - m >= 0) {
                 x = make_double2(r[m].x - iv[m] * x.x, r[m].y - iv[m] * x.y);
                 gstore2(s + (long long)(j1 - m) * nh, x);
+                sum += x.x;
             }
         }
 #pragma unroll
         for (int m = 0; m < TH_P; ++m) { r[m] = rn[m]; iv[m] = ivn[m]; }
     }
-    if (kx == 0 && kz == 0) {
-        // gauge: zero volume mean of p is zero mean of the (0,0) mode over y
-        double sum = 0.0;
-        for (int j = 0; j < ny; ++j) sum += gload2(s + (long long)j * nh).x;
-        const double m = sum / ny;
-        for (int j = 0; j < ny; ++j) {
-            const double2 v = gload2(s + (long long)j * nh);
-            gstore2(s + (long long)j * nh, make_double2(v.x - m, v.y));
-        }
-    }
+    // gauge: the volume mean of p is the mean over y of the (0, 0) mode (every other mode has zero
+    // mean over x and z); the inverse x transform subtracts it from p
+    if (kx == 0 && kz == 0) ((gptr<double>)D.gauge)[0] = sum / ny;
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -362,14 +358,16 @@ __global__ __launch_bounds__(NT) void k_ifftx(Batch B)
     __syncthreads();
     const int lp = tid / T, t = tid - (tid / T) * T;
     fft_stages<N, T, 0, 1>(buf + lp * N, 1, t, lp < LP, tw);
+    // walls: zero-mean gauge (the mean of the Neumann solution, from the tridiagonal solve)
+    const double pm = D.walls ? ((gptr<const double>)D.gauge)[0] : 0.0;
     for (int e = tid; e < LP * N; e += NT) {
         const int l2 = e / N, n = e - l2 * N;
         const int pair = pair0 + l2;
         if (pair >= npairs) continue;
         const double2 z = cconj(buf[e]);
         const int la = 2 * pair;
-        p[(long long)la * N + n] = z.x;
-        if (la + 1 < nlines) p[(long long)(la + 1) * N + n] = z.y;
+        p[(long long)la * N + n] = z.x - pm;
+        if (la + 1 < nlines) p[(long long)(la + 1) * N + n] = z.y - pm;
     }
 }
 
