@@ -231,8 +231,8 @@ __global__ __launch_bounds__(NT) void k_solve_periodic(Batch B)
 // walls: tridiagonal solve in y for every (kx, kz), pivots precomputed per (kx, |kz|)
 // ---------------------------------------------------------------------------------------------
 constexpr int TH_NT = 64;   // one wave per block: modes are few, spread them over all CUs
-constexpr int TH_P = 8;     // rows loaded ahead of the dependent recurrence
-
+// TH_P: rows loaded ahead of the dependent recurrence
+template <int TH_P>
 __global__ __launch_bounds__(TH_NT) void k_thomas(Batch B)
 {
     const Desc& D = *B.d[blockIdx.y];
@@ -510,7 +510,8 @@ hipError_t launch_thomas(const Batch& b, int nx, int ny, int nz, hipStream_t s)
 {
     const int cols = (nx / 2 + 1) * nz;
     dim3 grid((cols + TH_NT - 1) / TH_NT, b.count);
-    hipLaunchKernelGGL(k_thomas, grid, dim3(TH_NT), 0, s, b);
+    // 16 rows ahead (248 VGPRs, two waves per SIMD): measured best against 8 and 32
+    hipLaunchKernelGGL(k_thomas<16>, grid, dim3(TH_NT), 0, s, b);
     return hipGetLastError();
 }
 
