@@ -37,17 +37,27 @@ COUNTER_FILE = os.path.join(HERE, "profiles", "predictor_kolmogorov128_sq_counte
 RHEOLOGY_TEXT = {"kolmogorov128": "Saramito Wi=1 Bi=0.5 beta=0.5 Re=1000",
                  "channel_fene_p": "FENE-P L^2=900 Wi=5 beta=0.9 Re=2000",
                  "channel_saramito": "Saramito Wi=2 Bi=0.2 beta=0.1 Re=5000"}
-PRED_SOURCE = os.path.join(HERE, "paper_1803_09563_amd", "csrc", "k_predictor_zm.hip")
+PRED_SOURCES = [os.path.join(HERE, "paper_1803_09563_amd", "csrc", f)
+                for f in ("k_predictor_zm.hip", "weno.h")]
+
+
+def pred_source_hash():
+    """sha256[:16] of the predictor's sources (kernel file and its WENO header, concatenated)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in PRED_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(precision="double"):
     """HBM bytes per predictor launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary,
     or None if the kernel source changed since the counters were taken (or no summary exists)."""
-    import hashlib
     import re
     try:
         text = open(TRAFFIC_FILE).read()
-        sha = hashlib.sha256(open(PRED_SOURCE, "rb").read()).hexdigest()[:16]
+        sha = pred_source_hash()
     except OSError:
         return None
     m = re.search(r"sha256\[:16\] = ([0-9a-f]{16})", text)
@@ -60,11 +70,10 @@ def measured_traffic(precision="double"):
 def measured_valu_busy():
     """Fraction of SIMD cycles the FP64 predictor keeps the vector ALU busy, from the committed
     rocprofv3 SQ-counter summary, or None if the kernel source changed since it was taken."""
-    import hashlib
     import re
     try:
         text = open(COUNTER_FILE).read()
-        sha = hashlib.sha256(open(PRED_SOURCE, "rb").read()).hexdigest()[:16]
+        sha = pred_source_hash()
     except OSError:
         return None
     m = re.search(r"sha256\[:16\] = ([0-9a-f]{16})", text)
