@@ -193,16 +193,22 @@ __global__ __launch_bounds__(NT) void k_solve_periodic(Batch B)
     constexpr int T = strided_threads<N>();
     __shared__ double2 buf[N * TK];
     __shared__ double2 tw[N];
+    __shared__ double ez[N];        // Laplacian eigenvalues along z and of the block's kx columns
+    __shared__ double ex[TK];
     const Desc& D = *B.d[blockIdx.y];
     const int tid = threadIdx.x;
-    for (int n = tid; n < N; n += NT) tw[n] = gload2((gptr<const double2>)D.twz + n);
-    const gptr<double2> spec = (gptr<double2>)D.spec;
     const gptr<const double> eigx = (gptr<const double>)D.eigx;
     const gptr<const double> eigz = (gptr<const double>)D.eigz;
+    for (int n = tid; n < N; n += NT) {
+        tw[n] = gload2((gptr<const double2>)D.twz + n);
+        ez[n] = eigz[n];
+    }
+    const gptr<double2> spec = (gptr<double2>)D.spec;
     const int nh = D.nh, ny = D.ny;
     const int ntk = (nh + TK - 1) / TK;
     const int tile = blockIdx.x % ntk, ky = blockIdx.x / ntk;
     const int kx0 = tile * TK;
+    if (tid < TK) ex[tid] = kx0 + tid < nh ? eigx[kx0 + tid] : 0.0;
     const long long base = (long long)ky * nh + kx0, es = (long long)nh * ny;
     const bool colok = kx0 + tid % TK < nh;
     tile_in<N, false>(buf, spec + base, es, colok, tid);
@@ -216,7 +222,7 @@ __global__ __launch_bounds__(NT) void k_solve_periodic(Batch B)
         const int kx = kx0 + cc;
         double2 x = buf[e];
         if (kx < nh) {
-            const double den = eigx[kx] + ey + eigz[kz];
+            const double den = ex[cc] + ey + ez[kz];
             const double f = (kx == 0 && ky == 0 && kz == 0) ? 0.0 : scale / den;
             x = cscale(x, f);
         }
