@@ -88,9 +88,9 @@ __global__ __launch_bounds__(NT) void k_div_fftx(Batch B)
     const int pair0 = blockIdx.x * LP;
     const double idx = D.idx, idy = D.idy, idz = D.idz;
     const long long sxy = (long long)N * ny;
-    // divergence of u* on the block's lines; loads of two elements (12 values) are issued
+    // divergence of u* on the block's lines; loads of four elements (24 values) are issued
     // before their arithmetic and LDS stores
-    constexpr int M = (LP * N + NT - 1) / NT, G = M < 2 ? M : 2;
+    constexpr int M = (LP * N + NT - 1) / NT, G = M < 4 ? M : 4;
     const bool walls = D.walls != 0;
 #pragma unroll
     for (int g0 = 0; g0 < M; g0 += G) {
@@ -327,9 +327,9 @@ __global__ __launch_bounds__(NT) void k_ifftx(Batch B)
     const int npairs = (nlines + 1) >> 1;
     const int pair0 = blockIdx.x * LP;
     const int nh = D.nh;
-    // Hermitian extension of two half spectra into one complex line; loads of four elements are
+    // Hermitian extension of two half spectra into one complex line; loads of eight elements are
     // issued before their LDS stores
-    constexpr int M = (LP * N + NT - 1) / NT, G = M < 4 ? M : 4;
+    constexpr int M = (LP * N + NT - 1) / NT, G = M < 8 ? M : 8;
 #pragma unroll
     for (int g0 = 0; g0 < M; g0 += G) {
         double2 av[G], bv[G];
