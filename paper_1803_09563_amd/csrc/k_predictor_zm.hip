@@ -36,6 +36,20 @@ __device__ __forceinline__ int modp(int i, int n)
     return r < 0 ? r + n : r;
 }
 
+// Loads and stores at a wave-uniform base plus a per-thread byte offset that fits 32 bits
+// (within one plane of one field): the address is formed by the memory instruction from a scalar
+// base and a 32-bit vector offset, with no 64-bit vector arithmetic per access.
+template <typename T>
+__device__ __forceinline__ T ldb(gptr<const T> base, unsigned boff)
+{
+    return *(gptr<const T>)((gptr<const char>)base + boff);
+}
+template <typename T>
+__device__ __forceinline__ void stb(gptr<T> base, unsigned boff, T v)
+{
+    *(gptr<T>)((gptr<char>)base + boff) = v;
+}
+
 template <typename T> struct Smem {
     T B[6][RH][RW];      // B - I of plane k
     T gf[BH][BW];        // G F of plane k (G for Oldroyd-B / Saramito)
@@ -173,13 +187,15 @@ __global__ __launch_bounds__(NTH, (sizeof(T) == 4 && !WALLS) ? 3 : 2) void k_pre
     const Src os = bsrc(modp(i, nx), j);           // used only when the cell is outside the domain
     const VSrc ov = vsrc(modp(i, nx), j);
 
+    constexpr unsigned TS = sizeof(T);
     auto bload = [&](gptr<const T> p, int cc, const Src& q) {
-        T x = p[cc * ps + q.a];
-        if (WALLS) x = q.wa * x + q.wb * p[cc * ps + q.b];
+        T x = ldb<T>(p + cc * ps, (unsigned)q.a * TS);
+        if (WALLS) x = q.wa * x + q.wb * ldb<T>(p + cc * ps, (unsigned)q.b * TS);
         return x;
     };
     auto vload = [&](int kv, const VSrc& q, T* out) {
-        const double uu = gu[kv + q.o], vv = gv[kv + q.o], ww = gw[kv + q.o];
+        const unsigned o8 = (unsigned)q.o * 8u;
+        const double uu = ldb<double>(gu + kv, o8), vv = ldb<double>(gv + kv, o8), ww = ldb<double>(gw + kv, o8);
         if (!WALLS || q.kind == 0) { out[0] = (T)uu; out[1] = (T)vv; out[2] = (T)ww; }
         else if (q.kind == 3) { out[0] = (T)uu; out[1] = (T)0; out[2] = (T)ww; }
         else {
@@ -267,9 +283,9 @@ __global__ __launch_bounds__(NTH, (sizeof(T) == 4 && !WALLS) ? 3 : 2) void k_pre
     T win[7][6];
 #pragma unroll
     for (int m = 0; m < 6; ++m) {
-        const gptr<const T> p = Bin + modp(k0 - 3 + m, nz) * sxy + oij;
+        const gptr<const T> p = Bin + modp(k0 - 3 + m, nz) * sxy;
 #pragma unroll
-        for (int cc = 0; cc < 6; ++cc) win[m][cc] = p[cc * ps];
+        for (int cc = 0; cc < 6; ++cc) win[m][cc] = ldb<T>(p + cc * ps, (unsigned)oij * TS);
     }
     load_box(modp(k0 - 1, nz), win[2], (k0 + 2) % 3, 0, nullptr);
     load_box(k0, win[3], (k0 + 3) % 3, 0, nullptr);
@@ -282,9 +298,9 @@ __global__ __launch_bounds__(NTH, (sizeof(T) == 4 && !WALLS) ? 3 : 2) void k_pre
     for (int k = k0; k < k1; ++k) {
         const int kp = modp(k + 1, nz);
         {
-            const gptr<const T> p = Bin + modp(k + 3, nz) * sxy + oij;
+            const gptr<const T> p = Bin + modp(k + 3, nz) * sxy;
 #pragma unroll
-            for (int cc = 0; cc < 6; ++cc) win[6][cc] = p[cc * ps];
+            for (int cc = 0; cc < 6; ++cc) win[6][cc] = ldb<T>(p + cc * ps, (unsigned)oij * TS);
         }
         load_bplane(k, win[3]);
         load_box(kp, win[4], (k + 4) % 3, k, win[3]);
@@ -380,24 +396,29 @@ __global__ __launch_bounds__(NTH, (sizeof(T) == 4 && !WALLS) ? 3 : 2) void k_pre
             // every load of this cell's history and velocity is issued before any store: the
             // compiler cannot move a load above a store it cannot prove disjoint, and a wait for
             // a load also waits for the stores issued before it
+            // plane bases (uniform) and this cell's byte offsets within a plane
+            const int kq = k * sxy;
+            const unsigned ob = (unsigned)(j * nx + i) * TS, o8 = (unsigned)(j * nx + i) * 8u;
             T old[6];
 #pragma unroll
-            for (int cc = 0; cc < 6; ++cc) old[cc] = euler ? (T)0 : RT[cc * ps + q];
-            const double u0 = gu[q], v0 = gv[q], w0 = gw[q];
+            for (int cc = 0; cc < 6; ++cc) old[cc] = euler ? (T)0 : ldb<T>(RT + (kq + cc * ps), ob);
+            const double u0 = ldb<double>(gu + kq, o8), v0 = ldb<double>(gv + kq, o8), w0 = ldb<double>(gw + kq, o8);
             T ox = (T)0, oy = (T)0, oz = (T)0;
-            if (!euler && !freeze) { ox = RU[q]; oy = RU[ps + q]; oz = RU[2 * ps + q]; }
+            if (!euler && !freeze) {
+                ox = ldb<T>(RU + kq, ob); oy = ldb<T>(RU + (kq + ps), ob); oz = ldb<T>(RU + (kq + 2 * ps), ob);
+            }
 #pragma unroll
             for (int cc = 0; cc < 6; ++cc) {
-                Bout[cc * ps + q] = bt[cc] + dt * (c1 * rtv[cc] + c2 * old[cc]);
-                RT[cc * ps + q] = rtv[cc];
+                stb<T>(Bout + (kq + cc * ps), ob, bt[cc] + dt * (c1 * rtv[cc] + c2 * old[cc]));
+                stb<T>(RT + (kq + cc * ps), ob, rtv[cc]);
             }
 
             __asm__ volatile("" ::: "memory");
             if constexpr (TWOPH) {
                 // the two-phase momentum follows in k_momentum_two_phase
             } else if (freeze) {
-                gus[q] = u0; gvs[q] = v0; gws[q] = w0;
-                RU[q] = (T)0; RU[ps + q] = (T)0; RU[2 * ps + q] = (T)0;
+                stb<double>(gus + kq, o8, u0); stb<double>(gvs + kq, o8, v0); stb<double>(gws + kq, o8, w0);
+                stb<T>(RU + kq, ob, (T)0); stb<T>(RU + (kq + ps), ob, (T)0); stb<T>(RU + (kq + 2 * ps), ob, (T)0);
             } else {
                 // stresses of plane k from B - I and the staged factors
 #define TK(cc, di, dj) (fene ? (S.gf[rb + (dj)][cb + (di)] * S.B[cc][r + (dj)][c + (di)] + \
@@ -465,16 +486,16 @@ __global__ __launch_bounds__(NTH, (sizeof(T) == 4 && !WALLS) ? 3 : 2) void k_pre
 #undef TZ
                 if constexpr (RK3) {
                     // the stress divergence at B^k and any solid penalisation follow in k_stress_div
-                    gus[q] = u0 + (double)(dt * (mx * irho - c1 * rux - c2 * ox));
-                    gvs[q] = vwall ? 0.0 : v0 + (double)(dt * (my * irho - c1 * ruy - c2 * oy));
-                    gws[q] = w0 + (double)(dt * (mz * irho - c1 * ruz - c2 * oz));
+                    stb<double>(gus + kq, o8, u0 + (double)(dt * (mx * irho - c1 * rux - c2 * ox)));
+                    stb<double>(gvs + kq, o8, vwall ? 0.0 : v0 + (double)(dt * (my * irho - c1 * ruy - c2 * oy)));
+                    stb<double>(gws + kq, o8, w0 + (double)(dt * (mz * irho - c1 * ruz - c2 * oz)));
                 } else {
                     // a solid, if any, is applied by k_penalise once u* is complete
-                    gus[q] = u0 + (double)(dt * (c1 * rux + c2 * ox));
-                    gvs[q] = vwall ? 0.0 : v0 + (double)(dt * (c1 * ruy + c2 * oy));
-                    gws[q] = w0 + (double)(dt * (c1 * ruz + c2 * oz));
+                    stb<double>(gus + kq, o8, u0 + (double)(dt * (c1 * rux + c2 * ox)));
+                    stb<double>(gvs + kq, o8, vwall ? 0.0 : v0 + (double)(dt * (c1 * ruy + c2 * oy)));
+                    stb<double>(gws + kq, o8, w0 + (double)(dt * (c1 * ruz + c2 * oz)));
                 }
-                RU[q] = rux; RU[ps + q] = ruy; RU[2 * ps + q] = ruz;
+                stb<T>(RU + kq, ob, rux); stb<T>(RU + (kq + ps), ob, ruy); stb<T>(RU + (kq + 2 * ps), ob, ruz);
             }
 #undef VU
 #undef VV
