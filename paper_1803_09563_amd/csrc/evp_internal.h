@@ -86,7 +86,7 @@ hipError_t launch_fill(double* p, long long n, double value, hipStream_t s);
 hipError_t launch_stress_div(const Batch& b, int precision, int nx, int ny, int nz, bool walls,
                              hipStream_t s);
 hipError_t launch_penalise(const Batch& b, int nx, int ny, int nz, hipStream_t s);
-int predictor_chunk(int nx, int ny, int nz, bool three_per_cu);
+int predictor_chunk(int nx, int ny, int nz, bool four_per_cu);
 hipError_t launch_div_fftx(const Batch& b, int nx, int ny, int nz, hipStream_t s);
 hipError_t launch_fft_strided(const Batch& b, int nx, int ny, int nz, int axis, bool inverse,
                               hipStream_t s);

@@ -37,17 +37,34 @@ __device__ __forceinline__ int modp(int i, int n)
 }
 
 // Loads and stores at a wave-uniform base plus a per-thread byte offset that fits 32 bits
-// (within one plane of one field): the address is formed by the memory instruction from a scalar
-// base and a 32-bit vector offset, with no 64-bit vector arithmetic per access.
-template <typename T>
-__device__ __forceinline__ T ldb(gptr<const T> base, unsigned boff)
+// (within one plane of one field).  BUF: as raw buffer instructions, whose descriptor (base, no
+// stride, 2^31 - 1 bytes; fourth word the raw-buffer format of CDNA, 32-bit data, no swizzle)
+// lives in scalar registers, so an access costs no vector arithmetic and no 64-bit address
+// registers (this lets the FP32 kernel run four waves per SIMD); otherwise as global
+// instructions on the base plus the zero-extended offset (measured faster for the FP64 kernel).
+constexpr int kRawBufferWord3 = 0x00020000;
+template <bool BUF, typename T>
+__device__ __forceinline__ T ldx(gptr<const T> base, unsigned boff)
 {
-    return *(gptr<const T>)((gptr<const char>)base + boff);
+    if constexpr (BUF) {
+        const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc((EVP_GLOBAL void*)base, (short)0, 0x7fffffff, kRawBufferWord3);
+        if constexpr (sizeof(T) == 4) return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, boff, 0, 0));
+        else return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, boff, 0, 0));
+    } else {
+        return *(gptr<const T>)((gptr<const char>)base + boff);
+    }
 }
-template <typename T>
-__device__ __forceinline__ void stb(gptr<T> base, unsigned boff, T v)
+template <bool BUF, typename T>
+__device__ __forceinline__ void stx(gptr<T> base, unsigned boff, T v)
 {
-    *(gptr<T>)((gptr<char>)base + boff) = v;
+    if constexpr (BUF) {
+        typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+        const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc((EVP_GLOBAL void*)base, (short)0, 0x7fffffff, kRawBufferWord3);
+        if constexpr (sizeof(T) == 4) __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, boff, 0, 0);
+        else __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, boff, 0, 0);
+    } else {
+        *(gptr<T>)((gptr<char>)base + boff) = v;
+    }
 }
 
 template <typename T> struct Smem {
@@ -85,9 +102,12 @@ __device__ __forceinline__ T weno_up(T f0, T f1, T f2, T f3, T f4, T f5, T f6, T
 // TWOPH: two-phase mode (Sec. 3.2, FP64, AB2): lambda and G = mu_p/lambda of the cell come from
 // the mixture at phi^{n+1}; only the stress is advanced (the momentum has its own kernel).
 template <typename T, bool WALLS, int MODEL, bool RK3, bool HOUC, bool TWOPH>
-__global__ __launch_bounds__(NTH, (sizeof(T) == 4 && !WALLS) ? 3 : 2) void k_pred_zm(Batch B, int freeze, int kc, Rows rows)
+__global__ __launch_bounds__(NTH, (sizeof(T) == 4 && !WALLS) ? 4 : 2) void k_pred_zm(Batch B, int freeze, int kc, Rows rows)
 {
     __shared__ Smem<T> S;
+    // buffer-instruction accesses in the FP32 kernels and the FP64 wall kernel (which then keeps
+    // its ghost-row state in registers without spilling)
+    constexpr bool BUF = sizeof(T) == 4 || WALLS;
     const int b = blockIdx.y;
     const Desc& D = *B.d[b];
     const int nx = D.nx, ny = D.ny, nz = D.nz;
@@ -189,13 +209,13 @@ __global__ __launch_bounds__(NTH, (sizeof(T) == 4 && !WALLS) ? 3 : 2) void k_pre
 
     constexpr unsigned TS = sizeof(T);
     auto bload = [&](gptr<const T> p, int cc, const Src& q) {
-        T x = ldb<T>(p + cc * ps, (unsigned)q.a * TS);
-        if (WALLS) x = q.wa * x + q.wb * ldb<T>(p + cc * ps, (unsigned)q.b * TS);
+        T x = ldx<BUF, T>(p + cc * ps, (unsigned)q.a * TS);
+        if (WALLS) x = q.wa * x + q.wb * ldx<BUF, T>(p + cc * ps, (unsigned)q.b * TS);
         return x;
     };
     auto vload = [&](int kv, const VSrc& q, T* out) {
         const unsigned o8 = (unsigned)q.o * 8u;
-        const double uu = ldb<double>(gu + kv, o8), vv = ldb<double>(gv + kv, o8), ww = ldb<double>(gw + kv, o8);
+        const double uu = ldx<BUF, double>(gu + kv, o8), vv = ldx<BUF, double>(gv + kv, o8), ww = ldx<BUF, double>(gw + kv, o8);
         if (!WALLS || q.kind == 0) { out[0] = (T)uu; out[1] = (T)vv; out[2] = (T)ww; }
         else if (q.kind == 3) { out[0] = (T)uu; out[1] = (T)0; out[2] = (T)ww; }
         else {
@@ -285,7 +305,7 @@ __global__ __launch_bounds__(NTH, (sizeof(T) == 4 && !WALLS) ? 3 : 2) void k_pre
     for (int m = 0; m < 6; ++m) {
         const gptr<const T> p = Bin + modp(k0 - 3 + m, nz) * sxy;
 #pragma unroll
-        for (int cc = 0; cc < 6; ++cc) win[m][cc] = ldb<T>(p + cc * ps, (unsigned)oij * TS);
+        for (int cc = 0; cc < 6; ++cc) win[m][cc] = ldx<BUF, T>(p + cc * ps, (unsigned)oij * TS);
     }
     load_box(modp(k0 - 1, nz), win[2], (k0 + 2) % 3, 0, nullptr);
     load_box(k0, win[3], (k0 + 3) % 3, 0, nullptr);
@@ -300,7 +320,7 @@ __global__ __launch_bounds__(NTH, (sizeof(T) == 4 && !WALLS) ? 3 : 2) void k_pre
         {
             const gptr<const T> p = Bin + modp(k + 3, nz) * sxy;
 #pragma unroll
-            for (int cc = 0; cc < 6; ++cc) win[6][cc] = ldb<T>(p + cc * ps, (unsigned)oij * TS);
+            for (int cc = 0; cc < 6; ++cc) win[6][cc] = ldx<BUF, T>(p + cc * ps, (unsigned)oij * TS);
         }
         load_bplane(k, win[3]);
         load_box(kp, win[4], (k + 4) % 3, k, win[3]);
@@ -401,24 +421,24 @@ __global__ __launch_bounds__(NTH, (sizeof(T) == 4 && !WALLS) ? 3 : 2) void k_pre
             const unsigned ob = (unsigned)(j * nx + i) * TS, o8 = (unsigned)(j * nx + i) * 8u;
             T old[6];
 #pragma unroll
-            for (int cc = 0; cc < 6; ++cc) old[cc] = euler ? (T)0 : ldb<T>(RT + (kq + cc * ps), ob);
-            const double u0 = ldb<double>(gu + kq, o8), v0 = ldb<double>(gv + kq, o8), w0 = ldb<double>(gw + kq, o8);
+            for (int cc = 0; cc < 6; ++cc) old[cc] = euler ? (T)0 : ldx<BUF, T>(RT + (kq + cc * ps), ob);
+            const double u0 = ldx<BUF, double>(gu + kq, o8), v0 = ldx<BUF, double>(gv + kq, o8), w0 = ldx<BUF, double>(gw + kq, o8);
             T ox = (T)0, oy = (T)0, oz = (T)0;
             if (!euler && !freeze) {
-                ox = ldb<T>(RU + kq, ob); oy = ldb<T>(RU + (kq + ps), ob); oz = ldb<T>(RU + (kq + 2 * ps), ob);
+                ox = ldx<BUF, T>(RU + kq, ob); oy = ldx<BUF, T>(RU + (kq + ps), ob); oz = ldx<BUF, T>(RU + (kq + 2 * ps), ob);
             }
 #pragma unroll
             for (int cc = 0; cc < 6; ++cc) {
-                stb<T>(Bout + (kq + cc * ps), ob, bt[cc] + dt * (c1 * rtv[cc] + c2 * old[cc]));
-                stb<T>(RT + (kq + cc * ps), ob, rtv[cc]);
+                stx<BUF, T>(Bout + (kq + cc * ps), ob, bt[cc] + dt * (c1 * rtv[cc] + c2 * old[cc]));
+                stx<BUF, T>(RT + (kq + cc * ps), ob, rtv[cc]);
             }
 
             __asm__ volatile("" ::: "memory");
             if constexpr (TWOPH) {
                 // the two-phase momentum follows in k_momentum_two_phase
             } else if (freeze) {
-                stb<double>(gus + kq, o8, u0); stb<double>(gvs + kq, o8, v0); stb<double>(gws + kq, o8, w0);
-                stb<T>(RU + kq, ob, (T)0); stb<T>(RU + (kq + ps), ob, (T)0); stb<T>(RU + (kq + 2 * ps), ob, (T)0);
+                stx<BUF, double>(gus + kq, o8, u0); stx<BUF, double>(gvs + kq, o8, v0); stx<BUF, double>(gws + kq, o8, w0);
+                stx<BUF, T>(RU + kq, ob, (T)0); stx<BUF, T>(RU + (kq + ps), ob, (T)0); stx<BUF, T>(RU + (kq + 2 * ps), ob, (T)0);
             } else {
                 // stresses of plane k from B - I and the staged factors
 #define TK(cc, di, dj) (fene ? (S.gf[rb + (dj)][cb + (di)] * S.B[cc][r + (dj)][c + (di)] + \
@@ -486,16 +506,16 @@ __global__ __launch_bounds__(NTH, (sizeof(T) == 4 && !WALLS) ? 3 : 2) void k_pre
 #undef TZ
                 if constexpr (RK3) {
                     // the stress divergence at B^k and any solid penalisation follow in k_stress_div
-                    stb<double>(gus + kq, o8, u0 + (double)(dt * (mx * irho - c1 * rux - c2 * ox)));
-                    stb<double>(gvs + kq, o8, vwall ? 0.0 : v0 + (double)(dt * (my * irho - c1 * ruy - c2 * oy)));
-                    stb<double>(gws + kq, o8, w0 + (double)(dt * (mz * irho - c1 * ruz - c2 * oz)));
+                    stx<BUF, double>(gus + kq, o8, u0 + (double)(dt * (mx * irho - c1 * rux - c2 * ox)));
+                    stx<BUF, double>(gvs + kq, o8, vwall ? 0.0 : v0 + (double)(dt * (my * irho - c1 * ruy - c2 * oy)));
+                    stx<BUF, double>(gws + kq, o8, w0 + (double)(dt * (mz * irho - c1 * ruz - c2 * oz)));
                 } else {
                     // a solid, if any, is applied by k_penalise once u* is complete
-                    stb<double>(gus + kq, o8, u0 + (double)(dt * (c1 * rux + c2 * ox)));
-                    stb<double>(gvs + kq, o8, vwall ? 0.0 : v0 + (double)(dt * (c1 * ruy + c2 * oy)));
-                    stb<double>(gws + kq, o8, w0 + (double)(dt * (c1 * ruz + c2 * oz)));
+                    stx<BUF, double>(gus + kq, o8, u0 + (double)(dt * (c1 * rux + c2 * ox)));
+                    stx<BUF, double>(gvs + kq, o8, vwall ? 0.0 : v0 + (double)(dt * (c1 * ruy + c2 * oy)));
+                    stx<BUF, double>(gws + kq, o8, w0 + (double)(dt * (c1 * ruz + c2 * oz)));
                 }
-                stb<T>(RU + kq, ob, rux); stb<T>(RU + (kq + ps), ob, ruy); stb<T>(RU + (kq + 2 * ps), ob, ruz);
+                stx<BUF, T>(RU + kq, ob, rux); stx<BUF, T>(RU + (kq + ps), ob, ruy); stx<BUF, T>(RU + (kq + 2 * ps), ob, ruz);
             }
 #undef VU
 #undef VV
@@ -511,23 +531,23 @@ __global__ __launch_bounds__(NTH, (sizeof(T) == 4 && !WALLS) ? 3 : 2) void k_pre
 
 }  // namespace
 
-// planes per block: about as many blocks as can be resident (two per CU; three for the FP32
-// periodic kernel, whose registers allow three waves per SIMD), at least 4 planes per block
-int predictor_chunk_tiles(int tiles, int nz, bool three_per_cu)
+// planes per block: about as many blocks as can be resident (two per CU; four for the FP32
+// periodic kernel, whose registers and LDS allow four waves per SIMD), at least 4 planes per block
+int predictor_chunk_tiles(int tiles, int nz, bool four_per_cu)
 {
     static const int target_env = [] {
         const char* e = std::getenv("EVP_PRED_BLOCKS");
         return e ? std::atoi(e) : 0;
     }();
-    const int target = target_env > 0 ? target_env : (three_per_cu ? 768 : 512);
+    const int target = target_env > 0 ? target_env : (four_per_cu ? 1024 : 512);
     int nch = (target + tiles - 1) / tiles;
     nch = max(1, min(nch, nz / 4));
     return (nz + nch - 1) / nch;
 }
 
-int predictor_chunk(int nx, int ny, int nz, bool three_per_cu)
+int predictor_chunk(int nx, int ny, int nz, bool four_per_cu)
 {
-    return predictor_chunk_tiles(((nx + TX - 1) / TX) * ((ny + TY - 1) / TY), nz, three_per_cu);
+    return predictor_chunk_tiles(((nx + TX - 1) / TX) * ((ny + TY - 1) / TY), nz, four_per_cu);
 }
 
 hipError_t launch_predictor_zm(const Batch& b, int precision, int nx, int ny, int nz, bool freeze,
