@@ -49,7 +49,10 @@ __device__ __forceinline__ T weno5u(T v1, T v2, T v3, T v4, T v5, T eps2)
     const T q1 = (T)(5.0 / 6.0) * s2 - (T)(1.0 / 3.0) * s1;
     const T q2 = (T)(1.0 / 6.0) * s2 + (T)(1.0 / 3.0) * s3;
     const T q3 = (T)(2.0 / 3.0) * s3 - (T)(1.0 / 6.0) * s4;
-    return v3 + (w1 * q1 + w2 * q2 + w3 * q3) * fast_rcp(w1 + w2 + w3);
+    // FP32: the hardware reciprocal (about one ulp) is already at the precision of the FP32 sum;
+    // FP64 refines it to full precision
+    const T iw = sizeof(T) == 4 ? (T)__builtin_amdgcn_rcpf((float)(w1 + w2 + w3)) : fast_rcp(w1 + w2 + w3);
+    return v3 + (w1 * q1 + w2 * q2 + w3 * q3) * iw;
 }
 
 // regularised Heaviside of the two-phase mixture (Sec. 3.2.1): 0 below -e, 1 above e, smooth
