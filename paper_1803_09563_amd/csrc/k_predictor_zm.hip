@@ -92,6 +92,20 @@ __device__ __forceinline__ T weno_up(T f0, T f1, T f2, T f3, T f4, T f5, T f6, T
         return weno5u<T>(v1, v2, v3, v4, v5, eps2);
 }
 
+// upwind derivative (times h) from six values g0..g5 already in upwind order (for a negative
+// velocity the caller passes the stencil mirrored, f6..f1, and gets minus the derivative: the
+// scheme is odd in its differences, and every step of it is sign-symmetric in floating point)
+template <typename T, bool HOUC>
+__device__ __forceinline__ T weno_dir(T g0, T g1, T g2, T g3, T g4, T g5, T eps2)
+{
+    const T v1 = g1 - g0, v2 = g2 - g1, v3 = g3 - g2, v4 = g4 - g3, v5 = g5 - g4;
+    if constexpr (HOUC)
+        return (T)(2.0 / 60.0) * v1 - (T)(13.0 / 60.0) * v2 + (T)(47.0 / 60.0) * v3
+             + (T)(27.0 / 60.0) * v4 - (T)(3.0 / 60.0) * v5;
+    else
+        return weno5u<T>(v1, v2, v3, v4, v5, eps2);
+}
+
 // RK3: the substep of Sec. 3.3.1 instead of AB2.  B^k = B^{k-1} + dt (zeta RT^{k-1} + xi RT^{k-2});
 // the momentum part leaves out the stress divergence at the new level (added by k_stress_div once
 // B^k is complete) and the pressure gradient (the projection then yields p^k itself), and keeps
@@ -387,15 +401,33 @@ __global__ __launch_bounds__(NTH, (sizeof(T) == 4 && !WALLS) ? 4 : 2) void k_pre
             const int cm[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
             T rtv[6];
             {
+                // FP64: x and y stencils read from LDS in upwind order: element m of the x stencil
+                // is column c + sx (m - 3), of the y stencil row r + sy (m - 3), with s = +1 for a
+                // non-negative velocity and -1 otherwise; the sign of the derivative then comes
+                // with |velocity| in the advection term (no selects; bitwise the same numbers).
+                // FP32 keeps the selects: the per-thread LDS addresses cost it registers at four
+                // waves per SIMD.
+                constexpr bool MIRROR = sizeof(T) == 8;
+                const int sx = uc >= (T)0 ? 1 : -1, sy = vc >= (T)0 ? RW : -RW;
+                const T* const bx = &S.B[0][r][c];
+                const T auc = uc >= (T)0 ? uc : -uc, avc = vc >= (T)0 ? vc : -vc;
 #pragma unroll
                 for (int cc = 0; cc < 6; ++cc) {
-                    const T gx = weno_up<T, HOUC>(S.B[cc][r][c - 3], S.B[cc][r][c - 2], S.B[cc][r][c - 1], S.B[cc][r][c],
-                                                  S.B[cc][r][c + 1], S.B[cc][r][c + 2], S.B[cc][r][c + 3], uc, e2x);
-                    const T gy = weno_up<T, HOUC>(S.B[cc][r - 3][c], S.B[cc][r - 2][c], S.B[cc][r - 1][c], S.B[cc][r][c],
-                                                  S.B[cc][r + 1][c], S.B[cc][r + 2][c], S.B[cc][r + 3][c], vc, e2y);
+                    T gx, gy;
+                    if constexpr (MIRROR) {
+                        const T* const pc = bx + cc * (RH * RW);
+                        gx = weno_dir<T, HOUC>(pc[-3 * sx], pc[-2 * sx], pc[-sx], pc[0], pc[sx], pc[2 * sx], e2x);
+                        gy = weno_dir<T, HOUC>(pc[-3 * sy], pc[-2 * sy], pc[-sy], pc[0], pc[sy], pc[2 * sy], e2y);
+                    } else {
+                        gx = weno_up<T, HOUC>(S.B[cc][r][c - 3], S.B[cc][r][c - 2], S.B[cc][r][c - 1], S.B[cc][r][c],
+                                              S.B[cc][r][c + 1], S.B[cc][r][c + 2], S.B[cc][r][c + 3], uc, e2x);
+                        gy = weno_up<T, HOUC>(S.B[cc][r - 3][c], S.B[cc][r - 2][c], S.B[cc][r - 1][c], S.B[cc][r][c],
+                                              S.B[cc][r + 1][c], S.B[cc][r + 2][c], S.B[cc][r + 3][c], vc, e2y);
+                    }
                     const T gz = weno_up<T, HOUC>(win[0][cc], win[1][cc], win[2][cc], win[3][cc], win[4][cc],
                                                   win[5][cc], win[6][cc], wc, e2z);
-                    const T adv = uc * gx * idx + vc * gy * idy + wc * gz * idz;
+                    const T adv = MIRROR ? auc * gx * idx + avc * gy * idy + wc * gz * idz
+                                         : uc * gx * idx + vc * gy * idy + wc * gz * idz;
                     const int p = pa[cc], rr = pb[cc];
                     T ucv = L[p][rr] + L[rr][p];
 #pragma unroll
