@@ -276,11 +276,12 @@ constexpr double kRkXi[3] = {0.0, -17.0 / 60.0, -5.0 / 12.0};
 // The predictor is specialised per constitutive model and advection scheme: one launch per
 // (model, scheme) pair present in the batch, so a grid's arithmetic is the same alone and in any
 // batch.
-// the side stream of a channel grid, created on first use (default priority); nullptr if it
-// cannot be created, in which case the wall rows run after the interior on the main stream
+// the side stream of a channel grid in the mixed form (the only one that runs the predictor's
+// wall rows beside its interior), created on first use at default priority; nullptr otherwise or
+// if it cannot be created, in which case the wall rows run after the interior on the main stream
 const evp::Side* side_of(evp_grid* g)
 {
-    if (g->bc != EVP_WALLS) return nullptr;
+    if (g->bc != EVP_WALLS || g->precision != EVP_MIXED) return nullptr;
     if (!g->side_ready) {
         evp::Side sd{nullptr, nullptr, nullptr};
         if (hipStreamCreateWithFlags(&sd.s, hipStreamNonBlocking) != hipSuccess) return nullptr;
