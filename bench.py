@@ -154,6 +154,28 @@ def run_gpu(wl, precision, steps, warmup, quiet, integrator="ab2", adv=0, kappa=
     return {"ms": ms, "wall_s": wall, "prof": prof, "health": h}
 
 
+def d2d_copy_gbs(quiet, nbytes=1 << 30, reps=20):
+    """Bandwidth of the runtime's device-to-device copy (torch copy_, hipMemcpy path) of nbytes,
+    timed with events over reps copies; GB/s counts both directions.  A measured reference beside
+    the published 8 TB/s, not a peak: the step's own correction kernel streams faster."""
+    import torch
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    src.fill_(1)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    t1.record()
+    torch.cuda.synchronize()
+    gbs = 2.0 * nbytes * reps / (t0.elapsed_time(t1) * 1e-3) / 1e9
+    _log(f"device-to-device copy: {gbs:.0f} GB/s", quiet)
+    del src, dst
+    return gbs
+
+
 def serving(n_requests, quiet):
     """Rheology sweep served with continuous batching: a burst run (all requests at t = 0) gives
     the saturated throughput; a Poisson run at 0.7 of that request rate gives latencies."""
@@ -221,6 +243,7 @@ def main():
 
     f = res["fp64"]
     value = rate(f)
+    copy_gbs = d2d_copy_gbs(a.quiet)
     ms_step = f["ms"] / a.steps
     pk = f["prof"]["predictor"]
     pred_ms = pk["ms"] / max(pk["launches"], 1)
@@ -255,6 +278,8 @@ def main():
                      "kernel": "predictor (fused stress + momentum stencil)",
                      "bytes_per_cell": PRED_BYTES["fp64"], "avg_launch_us": pred_ms * 1e3},
         "step_hbm_frac": STEP_BYTES["fp64"] * value / 1e9 / HBM_PEAK_GBS,
+        "d2d_copy_gbs": copy_gbs,
+        "predictor_frac_of_d2d_copy": achieved / copy_gbs,
         "kernel_avg_us": kernels,
     }
     if "mixed" in res:
