@@ -197,6 +197,14 @@ int projection(evp_grid* g0, const Batch& b)
     const int nx = g0->nx, ny = g0->ny, nz = g0->nz;
     hipStream_t s = g0->stream;
     int r;
+    if (g0->bc == EVP_PERIODIC && evp::plane_transforms(nx, ny, nz, b.count)) {
+        // the x-y plane's half spectrum fits in LDS: x and y transforms fused per plane
+        if ((r = timed(g0, EVP_K_DIV_FFTX, [&] { return evp::launch_div_fftxy(b, nx, nz, s); }))) return r;
+        if ((r = timed(g0, EVP_K_SOLVE, [&] { return evp::launch_solve_periodic(b, nx, ny, nz, s); }))) return r;
+        if ((r = timed(g0, EVP_K_IFFTX, [&] { return evp::launch_ifftxy(b, nx, nz, s); }))) return r;
+        if ((r = timed(g0, EVP_K_CORRECT, [&] { return evp::launch_correct(b, nx, ny, nz, s); }))) return r;
+        return EVP_OK;
+    }
     if ((r = timed(g0, EVP_K_DIV_FFTX, [&] { return evp::launch_div_fftx(b, nx, ny, nz, s); }))) return r;
     if (g0->bc == EVP_PERIODIC) {
         if ((r = timed(g0, EVP_K_FFT_FWD, [&] { return evp::launch_fft_strided(b, nx, ny, nz, 1, false, s); }))) return r;

@@ -88,6 +88,12 @@ hipError_t launch_stress_div(const Batch& b, int precision, int nx, int ny, int 
 hipError_t launch_penalise(const Batch& b, int nx, int ny, int nz, hipStream_t s);
 int predictor_chunk(int nx, int ny, int nz, bool four_per_cu);
 hipError_t launch_div_fftx(const Batch& b, int nx, int ny, int nz, hipStream_t s);
+// periodic grids with nx == ny <= 128 and at least 256 z planes over the batch: divergence + x
+// and y transforms, and inverse y and x transforms, one block per z plane with the plane's half
+// spectrum in LDS
+bool plane_transforms(int nx, int ny, int nz, int count);
+hipError_t launch_div_fftxy(const Batch& b, int n, int nz, hipStream_t s);
+hipError_t launch_ifftxy(const Batch& b, int n, int nz, hipStream_t s);
 hipError_t launch_fft_strided(const Batch& b, int nx, int ny, int nz, int axis, bool inverse,
                               hipStream_t s);
 hipError_t launch_solve_periodic(const Batch& b, int nx, int ny, int nz, hipStream_t s);

@@ -7,7 +7,9 @@
 // Passes over the half spectrum S[kz][j][kx] (kx < nx/2+1, FP64 complex):
 //   periodic: div+fft(x) | fft(y) | fft(z), divide, ifft(z) | ifft(y) | ifft(x) -> p | correct
 //   walls:    div+fft(x) | fft(z) | Thomas(y)                | ifft(z) | ifft(x) -> p | correct
-// Real x-lines are transformed two at a time as one complex line (a + i b).
+// Real x-lines are transformed two at a time as one complex line (a + i b).  Periodic batches of
+// nx == ny <= 128 with enough z planes to fill the chip fuse the first two and the last two
+// periodic passes into one block per z plane, whose half-spectrum plane stays in LDS.
 #include "evp_internal.h"
 #include "fft_lds.h"
 
@@ -149,6 +151,191 @@ __global__ __launch_bounds__(NT) void k_div_fftx(Batch B)
         gstore2(spec + (long long)la * nh + k, make_double2(0.5 * s.x, 0.5 * s.y));
         if (la + 1 < nlines)
             gstore2(spec + (long long)(la + 1) * nh + k, make_double2(0.5 * d.y, -0.5 * d.x));
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// periodic grids whose x-y half-spectrum plane fits in LDS: one block per z plane does the
+// divergence and the forward x and y transforms in one pass, and the inverse y and x transforms
+// in another (the same line transforms, twiddles and two-for-one formulas as the separate
+// passes, so the same numbers, with two spectrum round trips and two launches fewer)
+// ---------------------------------------------------------------------------------------------
+constexpr int NTP = 1024;   // threads of the plane kernels
+
+// threads per y column: the largest of N/8, N/16, N/32 (at least 1) that lets all N/2 + 1 columns
+// of the plane be transformed at once
+template <int N>
+constexpr int plane_y_threads()
+{
+    int t = fft_threads<N>();
+    while (t > 1 && (N / 2 + 1) * t > NTP) t /= 2;
+    return t;
+}
+
+// y transforms of all nh columns of the plane in LDS (stride nh)
+template <int N>
+__device__ __forceinline__ void plane_y_fft(double2* buf, const double2* tw, int tid)
+{
+    constexpr int NH = N / 2 + 1, TY = plane_y_threads<N>();
+    static_assert(NH * TY <= NTP, "one pass of y transforms");
+    const int col = tid / TY, t = tid - (tid / TY) * TY;
+    fft_stages<N, TY, 0, 1>(buf + (col < NH ? col : 0), NH, t, col < NH, tw);
+}
+
+template <int N>
+__global__ __launch_bounds__(NTP) void k_div_fftxy(Batch B)
+{
+    constexpr int NH = N / 2 + 1, L = N / 2, TX = fft_threads<N>();
+    static_assert(L * TX <= NTP, "one pass of x transforms");
+    __shared__ double2 buf[N * NH];
+    __shared__ double2 twx[N], twy[N];
+    const Desc& D = *B.d[blockIdx.y];
+    const int tid = threadIdx.x, k = blockIdx.x;
+    for (int n = tid; n < N; n += NTP) {
+        twx[n] = gload2((gptr<const double2>)D.twx + n);
+        twy[n] = gload2((gptr<const double2>)D.twy + n);
+    }
+    const double sc = D.rho / B.dt[blockIdx.y];
+    const gptr<const double> us = (gptr<const double>)D.us;
+    const gptr<const double> vs = (gptr<const double>)D.vs;
+    const gptr<const double> ws = (gptr<const double>)D.ws;
+    const int nz = D.nz;
+    const long long sxy = (long long)N * N;
+    const double idx = D.idx, idy = D.idy, idz = D.idz;
+    // divergence of u* on the plane; complex line p holds rows 2p (real) and 2p + 1 (imaginary).
+    // Loads of four elements (24 values) are issued before their arithmetic and LDS stores.
+    constexpr int MD = (L * N + NTP - 1) / NTP, GD = MD < 4 ? MD : 4;
+#pragma unroll
+    for (int g0 = 0; g0 < MD; g0 += GD) {
+        double ld[GD][2][6];
+#pragma unroll
+        for (int m = 0; m < GD; ++m) {
+            const int e = tid + (g0 + m) * NTP;
+            const int ee = (g0 + m < MD && e < L * N) ? e : 0;
+            const int p = ee / N, i = ee - (ee / N) * N;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int j = 2 * p + h;
+                const long long q = ((long long)k * N + j) * N + i;
+                ld[m][h][0] = us[q];
+                ld[m][h][1] = us[q - i + wrapi(i - 1, N)];
+                ld[m][h][2] = vs[q];
+                ld[m][h][3] = (j > 0) ? vs[q - N] : vs[q + (long long)(N - 1) * N];
+                ld[m][h][4] = ws[q];
+                ld[m][h][5] = (k > 0) ? ws[q - sxy] : ws[q + (long long)(nz - 1) * sxy];
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < GD; ++m) {
+            const int e = tid + (g0 + m) * NTP;
+            if (g0 + m >= MD || e >= L * N) continue;
+            double r2[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const double* a = ld[m][h];
+                r2[h] = sc * ((a[0] - a[1]) * idx + (a[2] - a[3]) * idy + (a[4] - a[5]) * idz);
+            }
+            buf[e] = make_double2(r2[0], r2[1]);
+        }
+    }
+    __syncthreads();
+    {
+        const int lp = tid / TX, t = tid - (tid / TX) * TX;
+        fft_stages<N, TX, 0, 1>(buf + (lp < L ? lp : 0) * N, 1, t, lp < L, twx);
+    }
+    // two real spectra from each complex line, into rows j of the plane's half spectrum [j][kx]
+    constexpr int MS = (L * NH + NTP - 1) / NTP;
+    double2 za[MS], zb[MS];
+#pragma unroll
+    for (int m = 0; m < MS; ++m) {
+        const int e = tid + m * NTP;
+        if (e < L * NH) {
+            const int p = e / NH, kx = e - (e / NH) * NH;
+            const double2 Z = buf[p * N + kx];
+            const double2 Zc = cconj(buf[p * N + (kx == 0 ? 0 : N - kx)]);
+            const double2 sm = cadd(Z, Zc), d = csub(Z, Zc);
+            za[m] = make_double2(0.5 * sm.x, 0.5 * sm.y);
+            zb[m] = make_double2(0.5 * d.y, -0.5 * d.x);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < MS; ++m) {
+        const int e = tid + m * NTP;
+        if (e < L * NH) {
+            const int p = e / NH, kx = e - (e / NH) * NH;
+            buf[(2 * p) * NH + kx] = za[m];
+            buf[(2 * p + 1) * NH + kx] = zb[m];
+        }
+    }
+    __syncthreads();
+    plane_y_fft<N>(buf, twy, tid);
+    const gptr<double2> spec = (gptr<double2>)D.spec + (long long)k * N * NH;
+    for (int e = tid; e < N * NH; e += NTP) gstore2(spec + e, buf[e]);
+}
+
+template <int N>
+__global__ __launch_bounds__(NTP) void k_ifftxy(Batch B)
+{
+    constexpr int NH = N / 2 + 1, L = N / 2, TX = fft_threads<N>();
+    static_assert(L * TX <= NTP, "one pass of x transforms");
+    __shared__ double2 buf[N * NH];
+    __shared__ double2 twx[N], twy[N];
+    const Desc& D = *B.d[blockIdx.y];
+    const int tid = threadIdx.x, k = blockIdx.x;
+    for (int n = tid; n < N; n += NTP) {
+        twx[n] = gload2((gptr<const double2>)D.twx + n);
+        twy[n] = gload2((gptr<const double2>)D.twy + n);
+    }
+    // inverse y transform by conjugation on the way in and out
+    const gptr<const double2> spec = (gptr<const double2>)D.spec + (long long)k * N * NH;
+    {
+        constexpr int MS = (N * NH + NTP - 1) / NTP;
+        double2 v[MS];
+#pragma unroll
+        for (int m = 0; m < MS; ++m) {
+            const int e = tid + m * NTP;
+            v[m] = gload2(spec + (e < N * NH ? e : 0));
+        }
+#pragma unroll
+        for (int m = 0; m < MS; ++m) {
+            const int e = tid + m * NTP;
+            if (e < N * NH) buf[e] = cconj(v[m]);
+        }
+    }
+    __syncthreads();
+    plane_y_fft<N>(buf, twy, tid);
+    // Hermitian extension of rows 2p and 2p + 1 into complex line p (a + i b)
+    constexpr int ME = (L * N + NTP - 1) / NTP;
+    double2 ze[ME];
+#pragma unroll
+    for (int m = 0; m < ME; ++m) {
+        const int e = tid + m * NTP;
+        if (e < L * N) {
+            const int p = e / N, n = e - (e / N) * N;
+            const int kx = n <= N / 2 ? n : N - n;
+            double2 a = cconj(buf[(2 * p) * NH + kx]), b = cconj(buf[(2 * p + 1) * NH + kx]);
+            if (n > N / 2) { a = cconj(a); b = cconj(b); }
+            ze[m] = cconj(make_double2(a.x - b.y, a.y + b.x));
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < ME; ++m) {
+        const int e = tid + m * NTP;
+        if (e < L * N) buf[e] = ze[m];
+    }
+    __syncthreads();
+    {
+        const int lp = tid / TX, t = tid - (tid / TX) * TX;
+        fft_stages<N, TX, 0, 1>(buf + (lp < L ? lp : 0) * N, 1, t, lp < L, twx);
+    }
+    const gptr<double> p = (gptr<double>)D.p + (long long)k * N * N;
+    for (int e = tid; e < L * N; e += NTP) {
+        const int pr = e / N, n = e - (e / N) * N;
+        const double2 z = cconj(buf[e]);
+        p[(long long)(2 * pr) * N + n] = z.x;
+        p[(long long)(2 * pr + 1) * N + n] = z.y;
     }
 }
 
@@ -480,6 +667,40 @@ hipError_t launch_ifftx(const Batch& b, int nx, int ny, int nz, hipStream_t s)
     }
     EVP_FFT_SWITCH(nx, CALL)
 #undef CALL
+    return hipGetLastError();
+}
+
+bool plane_transforms(int nx, int ny, int nz, int count)
+{
+    // one block per z plane and at most one per CU at 128^2: with fewer planes than the chip's 256
+    // CUs the separate line-transform passes are as fast (measured on one 128^3 grid); with at
+    // least that many, the fused passes save 2-11 % of the step (batches of 32^3 to 128^3 grids)
+    const bool size = nx == ny && (nx == 16 || nx == 24 || nx == 32 || nx == 48 || nx == 64 ||
+                                   nx == 96 || nx == 128);
+    return size && (long long)nz * count >= 256;
+}
+
+hipError_t launch_div_fftxy(const Batch& b, int n, int nz, hipStream_t s)
+{
+    dim3 grid(nz, b.count);
+    switch (n) {
+#define CALL(N) case N: hipLaunchKernelGGL(k_div_fftxy<N>, grid, dim3(NTP), 0, s, b); break;
+    CALL(16) CALL(24) CALL(32) CALL(48) CALL(64) CALL(96) CALL(128)
+#undef CALL
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_ifftxy(const Batch& b, int n, int nz, hipStream_t s)
+{
+    dim3 grid(nz, b.count);
+    switch (n) {
+#define CALL(N) case N: hipLaunchKernelGGL(k_ifftxy<N>, grid, dim3(NTP), 0, s, b); break;
+    CALL(16) CALL(24) CALL(32) CALL(48) CALL(64) CALL(96) CALL(128)
+#undef CALL
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
