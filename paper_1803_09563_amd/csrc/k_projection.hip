@@ -203,7 +203,7 @@ __global__ __launch_bounds__(NTP) void k_div_fftxy(Batch B)
     const long long sxy = (long long)N * N;
     const double idx = D.idx, idy = D.idy, idz = D.idz;
     // divergence of u* on the plane; complex line p holds rows 2p (real) and 2p + 1 (imaginary).
-    // Loads of four elements (24 values) are issued before their arithmetic and LDS stores.
+    // Loads of four elements (48 values) are issued before their arithmetic and LDS stores.
     constexpr int MD = (L * N + NTP - 1) / NTP, GD = MD < 4 ? MD : 4;
 #pragma unroll
     for (int g0 = 0; g0 < MD; g0 += GD) {
