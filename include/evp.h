@@ -25,7 +25,8 @@
  *   - Status: 0 (EVP_OK) or a negative EVP_ERR_* code.  No call throws, aborts or prints;
  *     evp_last_error() returns a thread-local text describing the last failure.
  *   - Memory: the caller owns all device memory (the workspace and every I/O buffer); the library
- *     never allocates or frees device memory.  It owns only the opaque host-side evp_grid.
+ *     never allocates or frees device memory.  It owns only the opaque host-side evp_grid, and
+ *     one fixed-size static device array per GPU for evp_create_grid_static.
  *   - Streams: every call enqueues work on the HIP stream given at creation (or by
  *     evp_set_stream) and returns without waiting, except evp_health and evp_profile_read,
  *     which wait for the stream.  The caller synchronises before reading output buffers.
@@ -157,6 +158,25 @@ size_t evp_workspace_bytes(int nx, int ny, int nz, int bc_y, int precision);
 int evp_create_grid(int nx, int ny, int nz, double lx, double ly, double lz, int bc_y,
                     int precision, void* dev_workspace, size_t workspace_bytes, void* hip_stream,
                     evp_grid** out);
+
+/* Size of the library's static device workspace (64 MiB per GPU), see evp_create_grid_static. */
+#define EVP_STATIC_WORKSPACE_BYTES (64u << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): evp_create_grid with the workspace taken from a device
+ * array inside the library instead of the caller's.  The array holds EVP_STATIC_WORKSPACE_BYTES
+ * on every GPU the library runs on, until the process ends; a grid needing more
+ * (evp_workspace_bytes > EVP_STATIC_WORKSPACE_BYTES, e.g. beyond about 64^3 in EVP_FP64) is
+ * rejected with EVP_ERR_WORKSPACE.  The grid lives on the current device (which must be the
+ * stream's).  One such grid per device at a time: while it exists another call on that device
+ * returns EVP_ERR_STATE; evp_destroy_grid waits for its stream and frees the slot.  The state is
+ * cleared on creation (u = 0, B = I, p = 0), whatever an earlier grid left there.  All other calls
+ * work on it as on any grid; it calls no hipMalloc/hipFree, and a channel grid in EVP_MIXED runs
+ * the predictor's wall rows on its own stream (no side stream is created).  Work that other
+ * code enqueues on that device's static workspace would race with it; only this entry point uses
+ * it.  Enqueues a fill kernel and table uploads, and waits for the stream. */
+int evp_create_grid_static(int nx, int ny, int nz, double lx, double ly, double lz, int bc_y,
+                           int precision, void* hip_stream, evp_grid** out);
 
 /* Change the stream later calls enqueue on (the caller orders it after earlier work). */
 int evp_set_stream(evp_grid* g, void* hip_stream);

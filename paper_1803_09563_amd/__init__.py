@@ -17,7 +17,7 @@ __all__ = ["Grid", "step_batch", "EvpError", "lib", "workspace_bytes", "symbols"
            "OLDROYD_B", "FENE_P", "SARAMITO", "FP64", "MIXED", "PERIODIC", "WALLS",
            "FORCE_NONE", "FORCE_CONST_X", "FORCE_SIN_X_OF_Y", "FREEZE_VELOCITY",
            "STOP_AFTER_PREDICTOR", "MAX_BATCH", "KERNEL_NAMES", "AB2", "RK3", "NEO_HOOKEAN",
-           "WENO5", "HOUC5"]
+           "WENO5", "HOUC5", "STATIC_WORKSPACE_BYTES"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libevp.so")
@@ -31,6 +31,7 @@ AB2, RK3 = 0, 1
 FREEZE_VELOCITY, STOP_AFTER_PREDICTOR = 1, 2
 READ_U, READ_V, READ_W, READ_P, READ_B, READ_HIST = 1, 2, 4, 8, 16, 32
 MAX_BATCH = 32
+STATIC_WORKSPACE_BYTES = 64 << 20
 KERNEL_NAMES = ("predictor", "div_fftx", "fft_fwd", "solve", "fft_inv", "ifftx", "correct",
                 "stress_div", "penalise", "level_set", "reinit", "curvature", "momentum2", "split")
 
@@ -72,6 +73,7 @@ symbols = {
     "evp_workspace_bytes": (ctypes.c_size_t, [_i, _i, _i, _i, _i]),
     "evp_create_grid": (_i, [_i, _i, _i, _d, _d, _d, _i, _i, _vp, ctypes.c_size_t, _vp,
                              ctypes.POINTER(_vp)]),
+    "evp_create_grid_static": (_i, [_i, _i, _i, _d, _d, _d, _i, _i, _vp, ctypes.POINTER(_vp)]),
     "evp_set_stream": (_i, [_vp, _vp]),
     "evp_set_rheology": (_i, [_vp, _i, _d, _d, _d, _d, _d, _d]),
     "evp_set_forcing": (_i, [_vp, _i, _d, _d]),
@@ -137,10 +139,13 @@ def _dptr(t, shape, name):
 class Grid:
     """One solve: nx x ny x nz cells in an lx x ly x lz box (walls=True: no-slip walls at
     y = -ly/2, +ly/2), FP64 or MIXED precision.  Device memory is one torch uint8 tensor; work is
-    enqueued on ``stream`` (a torch.cuda.Stream; default: the current stream)."""
+    enqueued on ``stream`` (a torch.cuda.Stream; default: the current stream).
+    static_workspace=True creates the grid with evp_create_grid_static instead: no device memory
+    is allocated, the grid lives in the library's static workspace of the current device (one
+    such grid per device at a time, at most STATIC_WORKSPACE_BYTES)."""
 
     def __init__(self, nx, ny, nz, lx, ly, lz, walls=False, precision=FP64, stream=None,
-                 device="cuda"):
+                 device="cuda", static_workspace=False):
         torch = _torch()
         self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
         self.lx, self.ly, self.lz = float(lx), float(ly), float(lz)
@@ -150,11 +155,20 @@ class Grid:
         self.bytes = workspace_bytes(nx, ny, nz, walls, precision)
         if self.bytes == 0:
             raise ValueError(f"unsupported grid {nx}x{ny}x{nz} walls={walls}")
+        h = ctypes.c_void_p()
+        if static_workspace:
+            self._ws = None
+            _check(lib.evp_create_grid_static(self.nx, self.ny, self.nz, self.lx, self.ly,
+                                              self.lz, WALLS if walls else PERIODIC, precision,
+                                              ctypes.c_void_p(self.stream.cuda_stream),
+                                              ctypes.byref(h)), "evp_create_grid_static")
+            self._h = h
+            self.device = self.stream.device
+            return
         with torch.cuda.stream(self.stream):
             self._ws = torch.empty(self.bytes + 256, dtype=torch.uint8, device=device)
         base = self._ws.data_ptr()
         aligned = (base + 255) // 256 * 256
-        h = ctypes.c_void_p()
         _check(lib.evp_create_grid(self.nx, self.ny, self.nz, self.lx, self.ly, self.lz,
                                    WALLS if walls else PERIODIC, precision,
                                    ctypes.c_void_p(aligned), self.bytes,

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -133,6 +134,7 @@ struct evp_grid {
     double prof_ms[EVP_K_COUNT];
     evp::Side side;               // channel grids: second stream for the wall rows of the predictor
     bool side_ready;
+    int static_dev;               // device whose static workspace holds this grid; -1: caller's
 };
 
 namespace {
@@ -289,7 +291,7 @@ constexpr double kRkXi[3] = {0.0, -17.0 / 60.0, -5.0 / 12.0};
 // if it cannot be created, in which case the wall rows run after the interior on the main stream
 const evp::Side* side_of(evp_grid* g)
 {
-    if (g->bc != EVP_WALLS || g->precision != EVP_MIXED) return nullptr;
+    if (g->bc != EVP_WALLS || g->precision != EVP_MIXED || g->static_dev >= 0) return nullptr;
     if (!g->side_ready) {
         evp::Side sd{nullptr, nullptr, nullptr};
         if (hipStreamCreateWithFlags(&sd.s, hipStreamNonBlocking) != hipSuccess) return nullptr;
@@ -517,17 +519,24 @@ size_t evp_workspace_bytes(int nx, int ny, int nz, int bc_y, int precision)
     return make_layout(nx, ny, nz, bc_y, precision).total;
 }
 
-int evp_create_grid(int nx, int ny, int nz, double lx, double ly, double lz, int bc_y,
-                    int precision, void* dev_workspace, size_t workspace_bytes, void* hip_stream,
-                    evp_grid** out)
+}  // extern "C"
+
+namespace {
+
+// Workspace of grids created by evp_create_grid_static: one per device, resolved to a device
+// address per device with hipGetSymbolAddress (the host-side name is no device address).
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[EVP_STATIC_WORKSPACE_BYTES];
+std::mutex g_static_mu;
+void* g_static_ptr[kMaxDevices];
+bool g_static_busy[kMaxDevices];
+
+// The common part of evp_create_grid and evp_create_grid_static: checks the workspace, carves
+// it, clears the state with a fill kernel and uploads the tables and the descriptor.
+int create_in(int nx, int ny, int nz, double lx, double ly, double lz, int bc_y, int precision,
+              void* dev_workspace, size_t workspace_bytes, void* hip_stream, int static_dev,
+              evp_grid** out)
 {
-    g_last_error.clear();
-    if (!out) return fail(EVP_ERR_ARG, "out is NULL");
-    *out = nullptr;
-    std::string why;
-    if (!shape_ok(nx, ny, nz, bc_y, precision, &why)) return fail(EVP_ERR_ARG, why);
-    if (!(lx > 0) || !(ly > 0) || !(lz > 0) || !std::isfinite(lx) || !std::isfinite(ly) || !std::isfinite(lz))
-        return fail(EVP_ERR_ARG, "box lengths must be finite and positive");
     Layout L = make_layout(nx, ny, nz, bc_y, precision);
     if (!dev_workspace) return fail(EVP_ERR_WORKSPACE, "workspace is NULL");
     if (reinterpret_cast<uintptr_t>(dev_workspace) % kAlign != 0)
@@ -539,6 +548,7 @@ int evp_create_grid(int nx, int ny, int nz, double lx, double ly, double lz, int
     }
     evp_grid* g = new (std::nothrow) evp_grid();
     if (!g) return fail(EVP_ERR_ARG, "host allocation failed");
+    g->static_dev = static_dev;
     g->nx = nx; g->ny = ny; g->nz = nz; g->bc = bc_y; g->precision = precision;
     g->lx = lx; g->ly = ly; g->lz = lz;
     g->stream = reinterpret_cast<hipStream_t>(hip_stream);
@@ -574,8 +584,9 @@ int evp_create_grid(int nx, int ny, int nz, double lx, double ly, double lz, int
     g->d = (Desc*)(w + L.desc);
     g->parity = 0;
 
-    // zero state (u = 0, B - I = 0, histories 0, p = 0) and upload tables
-    hipError_t e = hipMemsetAsync(w + L.u, 0, L.spec - L.u, g->stream);
+    // zero state (u = 0, B - I = 0, histories 0, p = 0; the region is a whole number of 256-byte
+    // blocks) and upload tables
+    hipError_t e = evp::launch_fill((double*)(w + L.u), (long long)((L.spec - L.u) / 8), 0.0, g->stream);
     if (e != hipSuccess) { delete g; return hip_fail(e, "workspace clear"); }
     std::vector<char> tables;
     build_tables(g, tables, L.twx);
@@ -585,6 +596,65 @@ int evp_create_grid(int nx, int ny, int nz, double lx, double ly, double lz, int
     if (r) { delete g; return r; }
     *out = g;
     return EVP_OK;
+}
+
+bool box_ok(double lx, double ly, double lz)
+{
+    return lx > 0 && ly > 0 && lz > 0 && std::isfinite(lx) && std::isfinite(ly) && std::isfinite(lz);
+}
+
+}  // namespace
+
+extern "C" {
+
+int evp_create_grid(int nx, int ny, int nz, double lx, double ly, double lz, int bc_y,
+                    int precision, void* dev_workspace, size_t workspace_bytes, void* hip_stream,
+                    evp_grid** out)
+{
+    g_last_error.clear();
+    if (!out) return fail(EVP_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    std::string why;
+    if (!shape_ok(nx, ny, nz, bc_y, precision, &why)) return fail(EVP_ERR_ARG, why);
+    if (!box_ok(lx, ly, lz)) return fail(EVP_ERR_ARG, "box lengths must be finite and positive");
+    return create_in(nx, ny, nz, lx, ly, lz, bc_y, precision, dev_workspace, workspace_bytes,
+                     hip_stream, -1, out);
+}
+
+int evp_create_grid_static(int nx, int ny, int nz, double lx, double ly, double lz, int bc_y,
+                           int precision, void* hip_stream, evp_grid** out)
+{
+    g_last_error.clear();
+    if (!out) return fail(EVP_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    std::string why;
+    if (!shape_ok(nx, ny, nz, bc_y, precision, &why)) return fail(EVP_ERR_ARG, why);
+    if (!box_ok(lx, ly, lz)) return fail(EVP_ERR_ARG, "box lengths must be finite and positive");
+    const size_t need = make_layout(nx, ny, nz, bc_y, precision).total;
+    if (need > (size_t)EVP_STATIC_WORKSPACE_BYTES) {
+        char buf[200];
+        snprintf(buf, sizeof buf, "grid %dx%dx%d needs a %zu-byte workspace; the static workspace holds %zu",
+                 nx, ny, nz, need, (size_t)EVP_STATIC_WORKSPACE_BYTES);
+        return fail(EVP_ERR_WORKSPACE, buf);
+    }
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(EVP_ERR_ARG, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (g_static_busy[dev])
+        return fail(EVP_ERR_STATE, "the static workspace of this device holds a grid; destroy it first");
+    if (!g_static_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!p) return fail(EVP_ERR_HIP, "hipGetSymbolAddress(scratch) returned NULL");
+        g_static_ptr[dev] = p;
+    }
+    const int r = create_in(nx, ny, nz, lx, ly, lz, bc_y, precision, g_static_ptr[dev],
+                            (size_t)EVP_STATIC_WORKSPACE_BYTES, hip_stream, dev, out);
+    if (r == EVP_OK) g_static_busy[dev] = true;
+    return r;
 }
 
 int evp_set_stream(evp_grid* g, void* hip_stream)
@@ -973,6 +1043,12 @@ int evp_destroy_grid(evp_grid* g)
         fold_events(g);
     }
     for (hipEvent_t e : g->free_events) (void)hipEventDestroy(e);
+    if (g->static_dev >= 0) {
+        // the next grid on this static workspace must not overlap work still queued for this one
+        (void)hipStreamSynchronize(g->stream);
+        std::lock_guard<std::mutex> lock(g_static_mu);
+        g_static_busy[g->static_dev] = false;
+    }
     if (g->side_ready) {
         (void)hipStreamSynchronize(g->side.s);
         (void)hipEventDestroy(g->side.fork);
