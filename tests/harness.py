@@ -43,22 +43,35 @@ def oracle_state(s):
     return {"u": s.u, "v": s.v, "w": s.w, "p": s.p, "B": s.B}
 
 
-def field_errors(ref: dict, got: dict):
-    """Max errors: velocity components relative to the largest velocity magnitude, B - I
-    components relative to the largest |B - I|, p relative to max |p - mean p| (floored at
-    1e-6 rho U^2, so a flow whose pressure is identically zero compares rounding noise against
-    a physical pressure scale)."""
+# A field smaller than this share of its group's largest component (velocity components, the
+# six components of B - I) is compared against that share instead of its own maximum: its rounding
+# error comes from arithmetic on the larger components, so an own-scale figure for it would measure
+# the others' size, not its own accuracy.
+FLOOR = 1e-3
+
+
+def field_errors(ref: dict, got: dict, shared: bool = False):
+    """Max error of each field over the reference's max of that same field, |x - x_ref|_inf /
+    max(|x_ref|_inf, FLOOR * group scale), where the group scale is the largest velocity component
+    (u, v, w) or the largest |B - I| component (B); p is compared after removing its mean, against
+    max |p_ref - mean| floored at 1e-6 rho U^2 (a flow whose pressure is identically zero then
+    compares rounding noise against a physical pressure scale).  shared=True divides every field
+    by its group scale instead (the looser figure)."""
     err = {}
     vmax = max(np.abs(ref[k]).max() for k in ("u", "v", "w"))
     for k in ("u", "v", "w"):
-        err[k] = float(np.abs(got[k] - ref[k]).max() / max(vmax, 1e-300))
+        own = np.abs(ref[k]).max()
+        den = vmax if shared else max(own, FLOOR * vmax)
+        err[k] = float(np.abs(got[k] - ref[k]).max() / max(den, 1e-300))
     if "B" in ref and "B" in got:
         I6 = np.array([1.0, 0, 0, 1.0, 0, 1.0])[:, None, None, None]
         rb, gb = ref["B"] - I6, got["B"] - I6
         bmax = np.abs(rb).max()
         names = ("Bxx", "Bxy", "Bxz", "Byy", "Byz", "Bzz")
         for c in range(6):
-            err[names[c]] = float(np.abs(gb[c] - rb[c]).max() / max(bmax, 1e-300))
+            own = np.abs(rb[c]).max()
+            den = bmax if shared else max(own, FLOOR * bmax)
+            err[names[c]] = float(np.abs(gb[c] - rb[c]).max() / max(den, 1e-300))
     if "p" in ref and "p" in got:
         rp = ref["p"] - ref["p"].mean()
         gp = got["p"] - got["p"].mean()
@@ -67,7 +80,8 @@ def field_errors(ref: dict, got: dict):
 
 
 def assert_close(ref, got, tol, what="", p_tol=None):
-    """All fields within tol; the pressure within p_tol (default tol)."""
+    """All fields within tol (each against its own scale, see field_errors); the pressure within
+    p_tol (default tol)."""
     err = field_errors(ref, got)
     p_tol = tol if p_tol is None else p_tol
     bad = {k: v for k, v in err.items() if not (v <= (p_tol if k == "p" else tol))}
