@@ -278,8 +278,16 @@ int evp_save_state(evp_grid* g, void* dst, size_t bytes);
  * step continues exactly as the saved grid would have.  Waits for the stream. */
 int evp_load_state(evp_grid* g, const void* src, size_t bytes);
 
-/* Diagnostics of the current state; waits for the stream, *out is host memory. */
+/* Diagnostics of the current state; waits for the stream, *out is host memory.  The counts
+ * follow the trigger conditions of the local artificial diffusion of Sec. 3.1. */
 int evp_health(evp_grid* g, evp_health_t* out);
+
+/* evp_health without waiting: enqueues the same diagnostics on the grid's stream and writes the
+ * five values, as doubles in the order nonfinite, det_le0, trace_ge95, max_div, energy, into out5
+ * (device memory of 5 doubles, owned by the caller).  out5 is valid once the stream has passed
+ * this point (e.g. an event recorded after the call).  Same numbers as evp_health: the reduction
+ * sums in a fixed order. */
+int evp_health_enqueue(evp_grid* g, double* out5);
 
 /* Steps taken since the last evp_write_fields (AB2 bookkeeping). */
 int evp_step_count(evp_grid* g, long long* out);

@@ -94,6 +94,7 @@ symbols = {
     "evp_save_state": (_i, [_vp, _vp, ctypes.c_size_t]),
     "evp_load_state": (_i, [_vp, _vp, ctypes.c_size_t]),
     "evp_health": (_i, [_vp, ctypes.POINTER(_Health)]),
+    "evp_health_enqueue": (_i, [_vp, _vp]),
     "evp_step_count": (_i, [_vp, ctypes.POINTER(ctypes.c_longlong)]),
     "evp_profile": (_i, [_vp, _i]),
     "evp_profile_read": (_i, [_vp, ctypes.POINTER(_Profile)]),
@@ -187,6 +188,11 @@ class Grid:
 
     def set_stream(self, stream):
         _check(lib.evp_set_stream(self._h, ctypes.c_void_p(stream.cuda_stream)), "evp_set_stream")
+        # the workspaces are used on the new stream from now on: tell the caching allocator, so
+        # their memory is not handed to another allocation while work queued there still runs
+        for buf in (self._ws, getattr(self, "_ws2", None)):
+            if buf is not None:
+                buf.record_stream(stream)
         self.stream = stream
 
     def set_rheology(self, model, rho=1.0, mu_s=0.0, mu_p=0.0, lam=1.0, tau_y=0.0, L2=1.0e4):
@@ -306,6 +312,22 @@ class Grid:
         _check(lib.evp_health(self._h, ctypes.byref(h)), "evp_health")
         return {"nonfinite": h.nonfinite, "det_le0": h.det_le0, "trace_ge95": h.trace_ge95,
                 "max_div": h.max_div, "energy": h.energy}
+
+    def health_enqueue(self, out5):
+        """Enqueue the diagnostics on the grid's stream into out5, a float64 CUDA tensor of 5
+        values, valid once the stream has passed this point; read it with health_values()."""
+        torch = _torch()
+        if not (out5.is_cuda and out5.dtype == torch.float64 and out5.is_contiguous()
+                and out5.numel() >= 5):
+            raise ValueError("out5 must be a contiguous float64 CUDA tensor of 5 values")
+        _check(lib.evp_health_enqueue(self._h, ctypes.c_void_p(out5.data_ptr())),
+               "evp_health_enqueue")
+
+    @staticmethod
+    def health_values(out5):
+        v = [float(x) for x in out5[:5].cpu()]
+        return {"nonfinite": int(v[0]), "det_le0": int(v[1]), "trace_ge95": int(v[2]),
+                "max_div": v[3], "energy": v[4]}
 
     def step_count(self):
         n = ctypes.c_longlong()

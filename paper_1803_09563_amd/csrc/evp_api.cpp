@@ -919,7 +919,7 @@ int evp_health(evp_grid* g, evp_health_t* out)
 {
     if (int r = check_grid(g)) return r;
     if (!out) return fail(EVP_ERR_ARG, "out is NULL");
-    hipError_t e = evp::launch_health(g->d, g->precision, g->nx, g->ny, g->nz, g->parity, nullptr, g->stream);
+    hipError_t e = evp::launch_health(g->d, g->precision, g->parity, nullptr, g->stream);
     if (e != hipSuccess) return hip_fail(e, "health");
     double res[5];
     e = hipMemcpyAsync(res, g->h.red + 1024 * 5, sizeof res, hipMemcpyDeviceToHost, g->stream);
@@ -931,6 +931,15 @@ int evp_health(evp_grid* g, evp_health_t* out)
     out->trace_ge95 = (long long)res[2];
     out->max_div = res[3];
     out->energy = res[4];
+    return EVP_OK;
+}
+
+int evp_health_enqueue(evp_grid* g, double* out5)
+{
+    if (int r = check_grid(g)) return r;
+    if (!out5) return fail(EVP_ERR_ARG, "out5 is NULL");
+    hipError_t e = evp::launch_health(g->d, g->precision, g->parity, out5, g->stream);
+    if (e != hipSuccess) return hip_fail(e, "health");
     return EVP_OK;
 }
 

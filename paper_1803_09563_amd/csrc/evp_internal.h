@@ -86,7 +86,6 @@ hipError_t launch_fill(double* p, long long n, double value, hipStream_t s);
 hipError_t launch_stress_div(const Batch& b, int precision, int nx, int ny, int nz, bool walls,
                              hipStream_t s);
 hipError_t launch_penalise(const Batch& b, int nx, int ny, int nz, hipStream_t s);
-int predictor_chunk(int nx, int ny, int nz, bool four_per_cu);
 hipError_t launch_div_fftx(const Batch& b, int nx, int ny, int nz, hipStream_t s);
 // periodic grids with nx == ny <= 128 and at least 256 z planes over the batch: divergence + x
 // and y transforms, and inverse y and x transforms, one block per z plane with the plane's half
@@ -108,8 +107,7 @@ hipError_t launch_write_fields(const Desc* d, int precision, long long ncell, in
 hipError_t launch_read_fields(const Desc* d, int precision, long long ncell, int parity,
                               unsigned mask, double* u, double* v, double* w, double* p,
                               double* B6, double* hist, hipStream_t s);
-hipError_t launch_health(const Desc* d, int precision, int nx, int ny, int nz, int parity,
-                         double* partial_host_result, hipStream_t s);
+hipError_t launch_health(const Desc* d, int precision, int parity, double* out5, hipStream_t s);
 
 bool fft_size_supported(int n);
 

@@ -124,19 +124,37 @@ __global__ __launch_bounds__(HB) void k_health(const Desc* Dp, int parity)
     if (threadIdx.x < 5) D.red[blockIdx.x * 5 + threadIdx.x] = sh[threadIdx.x][0];
 }
 
-// fixed-order sum of the partials -> red[HBLOCKS*5 .. +5)
-__global__ __launch_bounds__(64) void k_health_final(const Desc* Dp, int nblocks)
+// Fixed-order reduction of the HBLOCKS partials -> red[HBLOCKS*5 .. +5) and, if out5 is not null,
+// out5[0..5): thread t folds the partials of blocks t, t + HB, t + 2 HB, ... in that order, then a
+// fixed pairwise tree over the threads, so every call sums in the same order (bitwise
+// reproducible).
+__global__ __launch_bounds__(HB) void k_health_final(const Desc* Dp, int nblocks, double* out5)
 {
     const Desc& D = *Dp;
-    if (threadIdx.x != 0) return;
+    const int t = threadIdx.x;
     double a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0;
-    for (int b = 0; b < nblocks; ++b) {
+    for (int b = t; b < nblocks; b += HB) {
         a0 += D.red[b * 5 + 0]; a1 += D.red[b * 5 + 1]; a2 += D.red[b * 5 + 2];
         a3 = fmax(a3, D.red[b * 5 + 3]); a4 += D.red[b * 5 + 4];
     }
-    double* o = D.red + HBLOCKS * 5;
-    o[0] = a0; o[1] = a1; o[2] = a2; o[3] = a3;
-    o[4] = 0.5 * a4 * D.dx * D.dy * D.dz;
+    __shared__ double sh[5][HB];
+    sh[0][t] = a0; sh[1][t] = a1; sh[2][t] = a2; sh[3][t] = a3; sh[4][t] = a4;
+    __syncthreads();
+    for (int s = HB / 2; s > 0; s >>= 1) {
+        if (t < s) {
+            sh[0][t] += sh[0][t + s];
+            sh[1][t] += sh[1][t + s];
+            sh[2][t] += sh[2][t + s];
+            sh[3][t] = fmax(sh[3][t], sh[3][t + s]);
+            sh[4][t] += sh[4][t + s];
+        }
+        __syncthreads();
+    }
+    if (t < 5) {
+        const double v = t == 4 ? 0.5 * sh[4][0] * D.dx * D.dy * D.dz : sh[t][0];
+        D.red[HBLOCKS * 5 + t] = v;
+        if (out5) out5[t] = v;
+    }
 }
 
 }  // namespace
@@ -166,21 +184,16 @@ hipError_t launch_read_fields(const Desc* d, int precision, long long ncell, int
     return hipGetLastError();
 }
 
-// Enqueues the reduction; the five results land at d->red + HBLOCKS*5 and are copied to
-// host_out (5 doubles) on the stream; the caller synchronises.
-hipError_t launch_health(const Desc* d, int precision, int nx, int ny, int nz, int parity,
-                         double* host_out, hipStream_t s)
+// Enqueues the reduction; the five results land at d->red + HBLOCKS*5 and, if out5 is not null,
+// in out5 (device memory or host memory the device can write); the caller synchronises.
+hipError_t launch_health(const Desc* d, int precision, int parity, double* out5, hipStream_t s)
 {
-    (void)nx; (void)ny; (void)nz;
     if (precision == EVP_MIXED)
         hipLaunchKernelGGL(k_health<float>, dim3(HBLOCKS), dim3(HB), 0, s, d, parity);
     else
         hipLaunchKernelGGL(k_health<double>, dim3(HBLOCKS), dim3(HB), 0, s, d, parity);
-    hipLaunchKernelGGL(k_health_final, dim3(1), dim3(64), 0, s, d, HBLOCKS);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    return hipSuccess;
-    (void)host_out;
+    hipLaunchKernelGGL(k_health_final, dim3(1), dim3(HB), 0, s, d, HBLOCKS, out5);
+    return hipGetLastError();
 }
 
 }  // namespace evp

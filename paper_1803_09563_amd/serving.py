@@ -9,8 +9,9 @@ loop
 * groups active solves by shape; each group owns a HIP stream and advances up to ``MAX_BATCH``
   solves per ``evp_step_batch`` launch, in chunks of a few steps, so groups of different shapes
   overlap on the device and new requests join at chunk boundaries;
-* retires a solve when its steps are done (health check; optional field copy) and frees its
-  workspace, which lets waiting requests in.
+* retires a solve when its steps are done: the health check (and the optional field copy) is
+  enqueued on the group's stream behind an event, the loop goes on, and once the event has
+  passed the solve's result is read and its workspace freed, which lets waiting requests in.
 
 Latency of a request = completion time - arrival time.  Every step runs in the library's kernels;
 this module only schedules.
@@ -100,6 +101,7 @@ class Server:
         self.n_active = 0
         self.peak_active = 0
         self.launches = 0
+        self.retiring = []           # (request, group, event, pinned health values, fields)
 
     # -- helpers --------------------------------------------------------------------------------
     def _prec(self, wl):
@@ -137,19 +139,39 @@ class Server:
         self.peak_used = max(self.peak_used, self.used)
         self.peak_active = max(self.peak_active, self.n_active)
 
-    def _retire(self, r: Request, grp: _Group, now):
+    def _begin_retire(self, r: Request, grp: _Group):
+        """Take a finished solve out of its group and enqueue its health check (and field copy)
+        on the group's stream behind an event; nothing waits here."""
+        torch = self.torch
         G = r.grid
-        h = G.health()           # synchronises the group's stream
+        grp.active.remove(r)
+        hv = torch.empty(5, dtype=torch.float64, pin_memory=True)
+        fields = None
+        with torch.cuda.stream(grp.stream):
+            hd = torch.empty(5, dtype=torch.float64, device=self.device)
+            G.health_enqueue(hd)
+            hv.copy_(hd, non_blocking=True)
+            if self.keep_fields:
+                dev = G.read_fields(("u", "v", "w", "p", "B"))
+                fields = {k: torch.empty(t.shape, dtype=t.dtype, pin_memory=True)
+                          for k, t in dev.items()}
+                for k, t in dev.items():
+                    fields[k].copy_(t, non_blocking=True)
+                    t.record_stream(grp.stream)
+            ev = torch.cuda.Event()
+            ev.record(grp.stream)
+        self.retiring.append((r, grp, ev, hv, fields))
+
+    def _finish_retire(self, item, now):
+        """The solve's event has passed: record its result, free its workspace and budget."""
+        r, grp, ev, hv, fields = item
+        h = Grid.health_values(hv)
         r.health = h
         r.status = "error" if (h["nonfinite"] > 0) else "done"
-        if self.keep_fields:
-            out = G.read_fields(("u", "v", "w", "p", "B"))
-            self.torch.cuda.current_stream().wait_stream(grp.stream)
-            grp.stream.synchronize()
-            r.fields = {k: t.cpu().numpy() for k, t in out.items()}
+        if fields is not None:
+            r.fields = {k: t.numpy() for k, t in fields.items()}
         r.finished = now
-        grp.active.remove(r)
-        G.close()
+        r.grid.close()
         r.grid = None
         self.used -= r.nbytes
         self.n_active -= 1
@@ -185,30 +207,39 @@ class Server:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         done = []
-        while pending or any(g.active for g in self.groups.values()):
+        while pending or self.retiring or any(g.active for g in self.groups.values()):
             now = time.perf_counter() - t0
             if time_limit is not None and now > time_limit:
                 raise TimeoutError("serving run exceeded its time limit")
             progressed = False
-            # 1. completed chunks -> step accounting, retirement
+            # 1. completed chunks -> step accounting; finished solves start retiring
             for grp in self.groups.values():
                 if grp.inflight is not None and grp.inflight[0].query():
                     for batch, k in grp.inflight[1]:
                         for r in batch:
                             r.remaining -= k
                     grp.inflight = None
-                    tnow = time.perf_counter() - t0
                     for r in [r for r in grp.active if r.remaining <= 0]:
-                        self._retire(r, grp, tnow)
-                        done.append(r)
+                        self._begin_retire(r, grp)
                     progressed = True
-            # 2. admission (FIFO: the head request blocks later ones until it fits)
+            # 2. retirements whose health check has completed free their workspace
+            if self.retiring:
+                still = []
+                for item in self.retiring:
+                    if item[2].query():
+                        self._finish_retire(item, time.perf_counter() - t0)
+                        done.append(item[0])
+                        progressed = True
+                    else:
+                        still.append(item)
+                self.retiring = still
+            # 3. admission (FIFO: the head request blocks later ones until it fits)
             now = time.perf_counter() - t0
             while (pending and pending[0].arrival <= now and self.n_active < self.max_active
                    and self.used + pending[0].nbytes <= self.budget):
                 self._admit(pending.popleft(), now)
                 progressed = True
-            # 3. launch the next chunk for every idle group
+            # 4. launch the next chunk for every idle group
             for grp in self.groups.values():
                 if grp.inflight is None and grp.active:
                     self._launch(grp)

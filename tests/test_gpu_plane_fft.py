@@ -67,7 +67,9 @@ def test_plane_batch_mixed_parity():
         assert_close(oracle_state(s), gpu_state(G), 1e-4, f"{wl.name} mixed batch, 20 steps", p_tol=1e-3)
 
 
-# 128^2 and 96^2 planes: the largest plane that fits in LDS, and a radix-3 length
+# 128^2 and 96^2 planes: the largest plane that fits in LDS, and a radix-3 length.  The fused
+# passes use the same transforms, twiddles and two-for-one formulas in the same order as the
+# separate passes, so every grid of the batch must equal the grid stepped alone bit for bit.
 @pytest.mark.parametrize("n,nz,count,precision", [(128, 8, 32, "fp64"), (96, 64, 4, "mixed"),
                                                   (64, 16, 16, "fp64")])
 def test_plane_batch_equals_single(n, nz, count, precision):
@@ -79,10 +81,11 @@ def test_plane_batch_equals_single(n, nz, count, precision):
         G.write_fields(*to_dev(*fields))
         batched.append(G)
     evp.step_batch(batched, 1e-3, 10)
-    tol = 1e-12 if precision == "fp64" else 1e-6
-    for (wl, fields), b in list(zip(cases, batched))[:3]:
+    for (wl, fields), b in zip(cases, batched):
         a = gpu_grid(wl)
         a.write_fields(*to_dev(*fields))
         a.step(1e-3, 10)
-        err = field_errors(gpu_state(a), gpu_state(b))
-        assert all(v <= tol for v in err.values()), (wl.name, err)
+        sa, sb = gpu_state(a), gpu_state(b)
+        a.close()
+        for k in sa:
+            assert np.array_equal(sa[k], sb[k]), (wl.name, k, field_errors(sa, sb))
