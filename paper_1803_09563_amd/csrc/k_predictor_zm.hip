@@ -115,10 +115,10 @@ __device__ __forceinline__ T weno_dir(T g0, T g1, T g2, T g3, T g4, T g5, T eps2
 // the WENO kernel's register allocation is not shared with the other scheme).
 // TWOPH: two-phase mode (Sec. 3.2, FP64, AB2): lambda and G = mu_p/lambda of the cell come from
 // the mixture at phi^{n+1}; only the stress is advanced (the momentum has its own kernel).
+// The block's work: tile `bid` of the tile rows `rows`, z-chunks of kc planes.
 template <typename T, bool WALLS, int MODEL, bool RK3, bool HOUC, bool TWOPH>
-__global__ __launch_bounds__(NTH, (sizeof(T) == 4 && !WALLS) ? 4 : 2) void k_pred_zm(Batch B, int freeze, int kc, Rows rows)
+__device__ __forceinline__ void pred_block(Smem<T>& S, const Batch& B, int freeze, int kc, Rows rows, int bid)
 {
-    __shared__ Smem<T> S;
     // buffer-instruction accesses in the FP32 kernels and the FP64 wall kernel (which then keeps
     // its ghost-row state in registers without spilling)
     constexpr bool BUF = sizeof(T) == 4 || WALLS;
@@ -129,7 +129,6 @@ __global__ __launch_bounds__(NTH, (sizeof(T) == 4 && !WALLS) ? 4 : 2) void k_pre
     const int ps = (int)D.ps;
     const int ntx = (nx + TX - 1) / TX, nty = rows.count, nch = (nz + kc - 1) / kc;
     const int nblk = ntx * nty * nch;
-    int bid = blockIdx.x;
     if ((nblk & 7) == 0) bid = (bid & 7) * (nblk >> 3) + (bid >> 3);     // XCD-contiguous tiles
     const int tile_x = bid % ntx, ch = bid / (ntx * nty);
     int tile_y = rows.first + (bid / ntx) % nty;
@@ -561,26 +560,44 @@ __global__ __launch_bounds__(NTH, (sizeof(T) == 4 && !WALLS) ? 4 : 2) void k_pre
     }
 }
 
+template <typename T, bool WALLS, int MODEL, bool RK3, bool HOUC, bool TWOPH>
+__global__ __launch_bounds__(NTH, (sizeof(T) == 4 && !WALLS) ? 4 : 2) void k_pred_zm(Batch B, int freeze, int kc, Rows rows)
+{
+    __shared__ Smem<T> S;
+    pred_block<T, WALLS, MODEL, RK3, HOUC, TWOPH>(S, B, freeze, kc, rows, blockIdx.x);
+}
+
+// FP64 channel: the rows next to the walls and the interior tile rows (periodic-in-y code) in one
+// grid, the first n_wall blocks the wall rows (the heavier blocks start first), the rest the
+// interior.  Both parts run two blocks per CU and take the same planes per block, so the blocks
+// of both parts share the rounds instead of the wall rows running after the interior.
+template <int MODEL, bool RK3, bool HOUC>
+__global__ __launch_bounds__(NTH, 2) void k_pred_zm_channel(Batch B, int freeze, int kc, Rows rows_int, Rows rows_wall, int n_wall)
+{
+    __shared__ Smem<double> S;
+    if ((int)blockIdx.x < n_wall) pred_block<double, true, MODEL, RK3, HOUC, false>(S, B, freeze, kc, rows_wall, blockIdx.x);
+    else pred_block<double, false, MODEL, RK3, HOUC, false>(S, B, freeze, kc, rows_int, blockIdx.x - n_wall);
+}
+
 }  // namespace
 
-// planes per block: about as many blocks as can be resident (two per CU; four for the FP32
-// periodic kernel, whose registers and LDS allow four waves per SIMD), at least 4 planes per block
-int predictor_chunk_tiles(int tiles, int nz, bool four_per_cu)
+// planes per block: `target` blocks per grid in total (EVP_PRED_BLOCKS overrides it), at least 4
+// planes per block.  Measured on one MI355X (blocks resident at once: two per CU for FP64, four
+// for the FP32 periodic kernel): periodic grids run best with about one round of resident blocks
+// (512 FP64, 1024 FP32), channels with about four rounds (2048), whose shorter z-chunks leave a
+// shorter last round
+int predictor_chunk_tiles(int tiles, int nz, int target)
 {
     static const int target_env = [] {
         const char* e = std::getenv("EVP_PRED_BLOCKS");
         return e ? std::atoi(e) : 0;
     }();
-    const int target = target_env > 0 ? target_env : (four_per_cu ? 1024 : 512);
+    if (target_env > 0) target = target_env;
     int nch = (target + tiles - 1) / tiles;
     nch = max(1, min(nch, nz / 4));
     return (nz + nch - 1) / nch;
 }
 
-int predictor_chunk(int nx, int ny, int nz, bool four_per_cu)
-{
-    return predictor_chunk_tiles(((nx + TX - 1) / TX) * ((ny + TY - 1) / TY), nz, four_per_cu);
-}
 
 hipError_t launch_predictor_zm(const Batch& b, int precision, int nx, int ny, int nz, bool freeze,
                                hipStream_t s, bool walls, int model, bool rk3, bool houc,
@@ -606,6 +623,32 @@ hipError_t launch_predictor_zm(const Batch& b, int precision, int nx, int ny, in
     // The rows next to the walls run beside the interior on the side stream in the mixed form
     // (measured faster for 256x128x128 and 512x256x256 channels); the FP64 wall kernel, which
     // keeps more state per thread, competes worse for the CUs and runs after the interior.
+    if (np == 2 && precision == EVP_FP64 && !two_phase) {
+        // one grid for both parts, chunked over all tile rows (see k_pred_zm_channel)
+        const int kc = predictor_chunk_tiles(ntx * nty, nz, 2048);
+        const int nch = (nz + kc - 1) / kc;
+        const int n_int = ntx * parts[0].rows.count * nch, n_wall = ntx * parts[1].rows.count * nch;
+        dim3 grid(n_int + n_wall, b.count);
+#define EVP_LAUNCH_C(MM, RR)                                                                       \
+    do {                                                                                           \
+        if (houc) hipLaunchKernelGGL((k_pred_zm_channel<MM, RR, true>), grid, dim3(NTH), 0, s, b, fz, kc, parts[0].rows, parts[1].rows, n_wall); \
+        else hipLaunchKernelGGL((k_pred_zm_channel<MM, RR, false>), grid, dim3(NTH), 0, s, b, fz, kc, parts[0].rows, parts[1].rows, n_wall); \
+    } while (0)
+#define EVP_LAUNCH_CR(MM)                                                                          \
+    do {                                                                                           \
+        if (rk3) EVP_LAUNCH_C(MM, true);                                                           \
+        else EVP_LAUNCH_C(MM, false);                                                              \
+    } while (0)
+        switch (model) {
+        case EVP_FENE_P: EVP_LAUNCH_CR(EVP_FENE_P); break;
+        case EVP_SARAMITO: EVP_LAUNCH_CR(EVP_SARAMITO); break;
+        case EVP_NEO_HOOKEAN: EVP_LAUNCH_CR(EVP_NEO_HOOKEAN); break;
+        default: EVP_LAUNCH_CR(EVP_OLDROYD_B); break;
+        }
+#undef EVP_LAUNCH_CR
+#undef EVP_LAUNCH_C
+        return hipGetLastError();
+    }
     const bool fork = np == 2 && side != nullptr && precision == EVP_MIXED;
     if (fork) {
         hipError_t e = hipEventRecord(side->fork, s);
@@ -616,7 +659,7 @@ hipError_t launch_predictor_zm(const Batch& b, int precision, int nx, int ny, in
     const bool pw = parts[ip].w;
     const Rows rows = parts[ip].rows;
     const hipStream_t ls = (fork && pw) ? side->s : s;
-    const int kc = predictor_chunk_tiles(ntx * rows.count, nz, precision == EVP_MIXED && !pw);
+    const int kc = predictor_chunk_tiles(ntx * rows.count, nz, walls ? 2048 : (precision == EVP_MIXED ? 1024 : 512));
     const int nblk = ntx * rows.count * ((nz + kc - 1) / kc);
     dim3 grid(nblk, b.count);
 #define EVP_LAUNCH2(TT, WW, MM, RR)                                                                \
