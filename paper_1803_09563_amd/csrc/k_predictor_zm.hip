@@ -43,27 +43,37 @@ __device__ __forceinline__ int modp(int i, int n)
 // registers (this lets the FP32 kernel run four waves per SIMD); otherwise as global
 // instructions on the base plus the zero-extended offset (measured faster for the FP64 kernel).
 constexpr int kRawBufferWord3 = 0x00020000;
-template <bool BUF, typename T>
+// Cache policy of an access.  kKeep: data that neighbouring tiles read again as their halo
+// (B - I, u, v, w).  kStream: data that only this cell touches in this kernel (the history it
+// reads, every result it writes); the non-temporal bit lets L2 evict those lines first, so the
+// halo lines of a plane survive until the neighbouring tiles have read them.  The value is the
+// non-temporal bit of the buffer instructions' cache-policy operand.
+constexpr int kKeep = 0, kStream = 2;
+template <bool BUF, typename T, int POL = kKeep>
 __device__ __forceinline__ T ldx(gptr<const T> base, unsigned boff)
 {
     if constexpr (BUF) {
         const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc((EVP_GLOBAL void*)base, (short)0, 0x7fffffff, kRawBufferWord3);
-        if constexpr (sizeof(T) == 4) return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, boff, 0, 0));
-        else return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, boff, 0, 0));
+        if constexpr (sizeof(T) == 4) return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, boff, 0, POL));
+        else return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, boff, 0, POL));
     } else {
-        return *(gptr<const T>)((gptr<const char>)base + boff);
+        const gptr<const T> a = (gptr<const T>)((gptr<const char>)base + boff);
+        if constexpr (POL == kStream) return __builtin_nontemporal_load(a);
+        else return *a;
     }
 }
-template <bool BUF, typename T>
+template <bool BUF, typename T, int POL = kStream>
 __device__ __forceinline__ void stx(gptr<T> base, unsigned boff, T v)
 {
     if constexpr (BUF) {
         typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
         const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc((EVP_GLOBAL void*)base, (short)0, 0x7fffffff, kRawBufferWord3);
-        if constexpr (sizeof(T) == 4) __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, boff, 0, 0);
-        else __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, boff, 0, 0);
+        if constexpr (sizeof(T) == 4) __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, boff, 0, POL);
+        else __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, boff, 0, POL);
     } else {
-        *(gptr<T>)((gptr<char>)base + boff) = v;
+        const gptr<T> a = (gptr<T>)((gptr<char>)base + boff);
+        if constexpr (POL == kStream) __builtin_nontemporal_store(v, a);
+        else *a = v;
     }
 }
 
@@ -452,11 +462,19 @@ __device__ __forceinline__ void pred_block(Smem<T>& S, const Batch& B, int freez
             const unsigned ob = (unsigned)(j * nx + i) * TS, o8 = (unsigned)(j * nx + i) * 8u;
             T old[6];
 #pragma unroll
-            for (int cc = 0; cc < 6; ++cc) old[cc] = euler ? (T)0 : ldx<BUF, T>(RT + (kq + cc * ps), ob);
-            const double u0 = ldx<BUF, double>(gu + kq, o8), v0 = ldx<BUF, double>(gv + kq, o8), w0 = ldx<BUF, double>(gw + kq, o8);
+            for (int cc = 0; cc < 6; ++cc) old[cc] = euler ? (T)0 : ldx<BUF, T, kStream>(RT + (kq + cc * ps), ob);
+            double u0, v0, w0;
+            if constexpr (!WALLS && sizeof(T) == 8) {
+                // this cell's velocities are in the ring slot of plane k (in FP64 the loaded values
+                // themselves), so they need no second load
+                u0 = VU(s0, 0, 0); v0 = VV(s0, 0, 0); w0 = VW(s0, 0, 0);
+            } else {
+                u0 = ldx<BUF, double>(gu + kq, o8); v0 = ldx<BUF, double>(gv + kq, o8); w0 = ldx<BUF, double>(gw + kq, o8);
+            }
             T ox = (T)0, oy = (T)0, oz = (T)0;
             if (!euler && !freeze) {
-                ox = ldx<BUF, T>(RU + kq, ob); oy = ldx<BUF, T>(RU + (kq + ps), ob); oz = ldx<BUF, T>(RU + (kq + 2 * ps), ob);
+                ox = ldx<BUF, T, kStream>(RU + kq, ob); oy = ldx<BUF, T, kStream>(RU + (kq + ps), ob);
+                oz = ldx<BUF, T, kStream>(RU + (kq + 2 * ps), ob);
             }
 #pragma unroll
             for (int cc = 0; cc < 6; ++cc) {

@@ -120,7 +120,9 @@ __global__ __launch_bounds__(SN) void k_stress_div(Batch B, int kc)
         double uo = 0.0, vo = 0.0, wo = 0.0;
         double pen[3] = {1.0, 1.0, 1.0};         // 1 - alpha of the solid fractions, if any
         if (valid) {
-            uo = us[q]; vo = vs[q]; wo = ws[q];
+            // u* is read and written once, by this cell: non-temporal, so L2 keeps the B halos
+            uo = __builtin_nontemporal_load(us + q); vo = __builtin_nontemporal_load(vs + q);
+            wo = __builtin_nontemporal_load(ws + q);
             if (solid)
                 for (int m = 0; m < 3; ++m) pen[m] = 1.0 - ((gptr<const double>)D.alpha[m])[q];
         }
@@ -135,19 +137,19 @@ __global__ __launch_bounds__(SN) void k_stress_div(Batch B, int kc)
             const T dx_ = (TA(P0, 0, 1, 0) - TA(P0, 0, 0, 0)) * idx
                         + qt * (TA(P0, 1, 0, 1) + TA(P0, 1, 1, 1) - TA(P0, 1, 0, -1) - TA(P0, 1, 1, -1)) * idy
                         + qt * (TA(Pp, 2, 0, 0) + TA(Pp, 2, 1, 0) - TA(Pm, 2, 0, 0) - TA(Pm, 2, 1, 0)) * idz;
-            us[q] = (uo + (double)(c * dx_)) * pen[0];
+            __builtin_nontemporal_store((uo + (double)(c * dx_)) * pen[0], us + q);
             // y-face (i, j+1/2, k); the top wall face stays 0
             if (!vwall) {
                 const T dy_ = qt * (TA(P0, 1, 1, 0) + TA(P0, 1, 1, 1) - TA(P0, 1, -1, 0) - TA(P0, 1, -1, 1)) * idx
                             + (TA(P0, 3, 0, 1) - TA(P0, 3, 0, 0)) * idy
                             + qt * (TA(Pp, 4, 0, 0) + TA(Pp, 4, 0, 1) - TA(Pm, 4, 0, 0) - TA(Pm, 4, 0, 1)) * idz;
-                vs[q] = (vo + (double)(c * dy_)) * pen[1];
+                __builtin_nontemporal_store((vo + (double)(c * dy_)) * pen[1], vs + q);
             }
             // z-face (i, j, k+1/2)
             const T dz_ = qt * (TA(P0, 2, 1, 0) + TA(Pp, 2, 1, 0) - TA(P0, 2, -1, 0) - TA(Pp, 2, -1, 0)) * idx
                         + qt * (TA(P0, 4, 0, 1) + TA(Pp, 4, 0, 1) - TA(P0, 4, 0, -1) - TA(Pp, 4, 0, -1)) * idy
                         + (TA(Pp, 5, 0, 0) - TA(P0, 5, 0, 0)) * idz;
-            ws[q] = (wo + (double)(c * dz_)) * pen[2];
+            __builtin_nontemporal_store((wo + (double)(c * dz_)) * pen[2], ws + q);
 #undef TA
         }
         __syncthreads();
