@@ -69,7 +69,8 @@ def test_plane_batch_mixed_parity():
 
 # 128^2 and 96^2 planes: the largest plane that fits in LDS, and a radix-3 length.  The fused
 # passes use the same transforms, twiddles and two-for-one formulas in the same order as the
-# separate passes, so every grid of the batch must equal the grid stepped alone bit for bit.
+# separate passes, so every grid of the batch must equal the grid stepped alone bit for bit; the
+# first grid is also compared with the oracle.
 @pytest.mark.parametrize("n,nz,count,precision", [(128, 8, 32, "fp64"), (96, 64, 4, "mixed"),
                                                   (64, 16, 16, "fp64")])
 def test_plane_batch_equals_single(n, nz, count, precision):
@@ -81,6 +82,16 @@ def test_plane_batch_equals_single(n, nz, count, precision):
         G.write_fields(*to_dev(*fields))
         batched.append(G)
     evp.step_batch(batched, 1e-3, 10)
+    # the fused passes at this plane size against the oracle too (first grid of the batch)
+    wl0, fields0 = cases[0]
+    s = oracle_solver(wl0)
+    s.write_fields(*fields0)
+    s.step(1e-3, 10)
+    if precision == "fp64":
+        assert_close(oracle_state(s), gpu_state(batched[0]), 1e-10, f"{wl0.name} FP64 fused passes, 10 steps")
+    else:
+        assert_close(oracle_state(s), gpu_state(batched[0]), 1e-4, f"{wl0.name} mixed fused passes, 10 steps",
+                     p_tol=1e-3)
     for (wl, fields), b in zip(cases, batched):
         a = gpu_grid(wl)
         a.write_fields(*to_dev(*fields))
