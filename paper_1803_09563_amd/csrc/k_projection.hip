@@ -571,7 +571,13 @@ __global__ __launch_bounds__(256) void k_correct(Batch B)
 {
     const Desc& D = *B.d[blockIdx.y];
     const int nx = D.nx, ny = D.ny, nz = D.nz;
-    const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
+    // consecutive blocks on one XCD (the hardware deals blocks round-robin over the eight XCDs),
+    // so the rows j + 1 and the plane k + 1 whose p this block reads are read by blocks of the
+    // same XCD's L2
+    const int nb = gridDim.x;
+    int bid = blockIdx.x;
+    if ((nb & 7) == 0) bid = (bid & 7) * (nb >> 3) + (bid >> 3);
+    const long long q = (long long)bid * 256 + threadIdx.x;
     if (q >= D.ncell) return;
     const int i = (int)(q % nx);
     const long long r = q / nx;
