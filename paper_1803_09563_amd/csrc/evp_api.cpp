@@ -76,11 +76,17 @@ bool shape_ok(int nx, int ny, int nz, int bc_y, int precision, std::string* why)
     return true;
 }
 
+// row stride of the half spectrum (and of the pivot table): nx/2 + 1 complex values rounded up
+// to 8, so that the 16-column tiles of the strided passes and the mode rows of the Thomas sweep
+// start on 128-byte lines
+size_t spectrum_stride(int nx) { return ((size_t)nx / 2 + 1 + 7) / 8 * 8; }
+
 Layout make_layout(int nx, int ny, int nz, int bc_y, int precision)
 {
     Layout L{};
     const size_t n = (size_t)nx * ny * nz;
     const size_t nh = (size_t)nx / 2 + 1;
+    const size_t sh = spectrum_stride(nx);
     const size_t tsz = precision == EVP_MIXED ? 4 : 8;
     L.ps = (long long)((n + 63) / 64 * 64);
     size_t off = 0;
@@ -93,10 +99,10 @@ Layout make_layout(int nx, int ny, int nz, int bc_y, int precision)
     L.B1 = take(6 * (size_t)L.ps * tsz);
     L.RT = take(6 * (size_t)L.ps * tsz);
     L.RU = take(3 * (size_t)L.ps * tsz);
-    L.spec = take(nh * ny * nz * 16);
+    L.spec = take(sh * ny * nz * 16);
     L.twx = take((size_t)nx * 16); L.twy = take((size_t)ny * 16); L.twz = take((size_t)nz * 16);
     L.eigx = take(nh * 8); L.eigy = take((size_t)ny * 8); L.eigz = take((size_t)nz * 8);
-    L.piv = take(bc_y == EVP_WALLS ? ((size_t)nz / 2 + 1) * ny * nh * 8 : 8);
+    L.piv = take(bc_y == EVP_WALLS ? ((size_t)nz / 2 + 1) * ny * sh * 8 : 8);
     L.red = take(kRedDoubles * 8);
     L.gauge = take(8);
     L.total = off;
@@ -254,6 +260,7 @@ void build_tables(const evp_grid* g, std::vector<char>& host, size_t base)
         const double* ez = reinterpret_cast<const double*>(host.data() + (L.eigz - base));
         double* piv = reinterpret_cast<double*>(host.data() + (L.piv - base));
         const int ny = g->ny;
+        const size_t sh = spectrum_stride(g->nx);
         const double a = 1.0 / (g->h.dy * g->h.dy);
         for (int kzs = 0; kzs <= g->nz / 2; ++kzs) {
             for (int kx = 0; kx < nh; ++kx) {
@@ -263,10 +270,10 @@ void build_tables(const evp_grid* g, std::vector<char>& host, size_t base)
                     double bj = -2.0 * a + mu;
                     if (j == 0 || j == ny - 1) bj += a;
                     const double inv = 1.0 / (bj - a * cprev);
-                    piv[((size_t)kzs * ny + j) * nh + kx] = inv;
+                    piv[((size_t)kzs * ny + j) * sh + kx] = inv;
                     cprev = a * inv;
                 }
-                if (kx == 0 && kzs == 0) piv[(size_t)(ny - 1) * nh] = 0.0;   // singular mode: p_{ny-1} = 0
+                if (kx == 0 && kzs == 0) piv[(size_t)(ny - 1) * sh] = 0.0;   // singular mode: p_{ny-1} = 0
             }
         }
     }
@@ -557,7 +564,7 @@ int create_in(int nx, int ny, int nz, double lx, double ly, double lz, int bc_y,
     g->L = L;
     Desc& h = g->h;
     std::memset(&h, 0, sizeof h);
-    h.nx = nx; h.ny = ny; h.nz = nz; h.nh = nx / 2 + 1;
+    h.nx = nx; h.ny = ny; h.nz = nz; h.nh = nx / 2 + 1; h.sh = (int)spectrum_stride(nx);
     h.walls = bc_y == EVP_WALLS;
     h.precision = precision;
     h.model = EVP_OLDROYD_B;

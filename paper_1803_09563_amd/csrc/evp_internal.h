@@ -18,6 +18,8 @@ struct Desc {
     int model;                   // EVP_OLDROYD_B / EVP_FENE_P / EVP_SARAMITO / EVP_NEO_HOOKEAN
     int force_kind;              // EVP_FORCE_*
     int adv;                     // EVP_WENO5 / EVP_HOUC5
+    int sh;                      // row stride of the half spectrum and the pivots: nh rounded up
+                                 // to 8 complex values, so every row starts on a 128-byte line
     double kappa;                // artificial diffusion coefficient (0: off)
     const double* alpha[3];      // solid volume fractions at u, v, w points (caller's; null: none)
     // two-phase (bubbly-flow) mode, Sec. 3.2: properties of fluid 1 (phi > 0) and fluid 2, the
@@ -38,10 +40,10 @@ struct Desc {
     void* RT;                    // stress right-hand side history, six planes (double or float)
     void* RU;                    // momentum right-hand side history, three planes
     double* p;                   // pressure
-    double2* spec;               // half spectrum [nz][ny][nh]
+    double2* spec;               // half spectrum [nz][ny][sh] (kx < nh used)
     const double2 *twx, *twy, *twz;        // W_N^n = exp(-2 pi i n / N), n < N, per direction
     const double *eigx, *eigy, *eigz;      // -(4/h^2) sin^2(pi k / N) per direction
-    const double* piv;           // walls: Thomas pivots 1/(b_j - a c'_{j-1}) [nz/2+1][ny][nh]
+    const double* piv;           // walls: Thomas pivots 1/(b_j - a c'_{j-1}) [nz/2+1][ny][sh]
     double* red;                 // reduction partials (health)
     double* gauge;               // walls: volume mean of p before the zero-mean gauge (one value)
 };

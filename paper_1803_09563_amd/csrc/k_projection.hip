@@ -4,7 +4,8 @@
 // directions (eigenvalues -(4/h^2) sin^2(pi k/N)); across walls (homogeneous Neumann rows) each
 // (kx, kz) mode is a tridiagonal system in y solved by a Thomas sweep.
 //
-// Passes over the half spectrum S[kz][j][kx] (kx < nx/2+1, FP64 complex):
+// Passes over the half spectrum S[kz][j][kx] (kx < nx/2+1, FP64 complex; rows padded to a
+// multiple of 8 values, 128 bytes):
 //   periodic: div+fft(x) | fft(y) | fft(z), divide, ifft(z) | ifft(y) | ifft(x) -> p | correct
 //   walls:    div+fft(x) | fft(z) | Thomas(y)                | ifft(z) | ifft(x) -> p | correct
 // Real x-lines are transformed two at a time as one complex line (a + i b).  Periodic batches of
@@ -139,7 +140,7 @@ __global__ __launch_bounds__(NT) void k_div_fftx(Batch B)
     __syncthreads();
     const int lp = tid / T, t = tid - (tid / T) * T;
     fft_stages<N, T, 0, 1>(buf + lp * N, 1, t, lp < LP, tw);
-    const int nh = D.nh;
+    const int sh = D.sh;
     for (int e = tid; e < LP * NHF; e += NT) {
         const int l2 = e / NHF, k = e - l2 * NHF;
         const int pair = pair0 + l2;
@@ -148,9 +149,9 @@ __global__ __launch_bounds__(NT) void k_div_fftx(Batch B)
         const double2 Zc = cconj(buf[l2 * N + (k == 0 ? 0 : N - k)]);
         const double2 s = cadd(Z, Zc), d = csub(Z, Zc);
         const int la = 2 * pair;
-        gstore2(spec + (long long)la * nh + k, make_double2(0.5 * s.x, 0.5 * s.y));
+        gstore2(spec + (long long)la * sh + k, make_double2(0.5 * s.x, 0.5 * s.y));
         if (la + 1 < nlines)
-            gstore2(spec + (long long)(la + 1) * nh + k, make_double2(0.5 * d.y, -0.5 * d.x));
+            gstore2(spec + (long long)(la + 1) * sh + k, make_double2(0.5 * d.y, -0.5 * d.x));
     }
 }
 
@@ -270,8 +271,12 @@ __global__ __launch_bounds__(NTP) void k_div_fftxy(Batch B)
     }
     __syncthreads();
     plane_y_fft<N>(buf, twy, tid);
-    const gptr<double2> spec = (gptr<double2>)D.spec + (long long)k * N * NH;
-    for (int e = tid; e < N * NH; e += NTP) gstore2(spec + e, buf[e]);
+    const int sh = D.sh;
+    const gptr<double2> spec = (gptr<double2>)D.spec + (long long)k * N * sh;
+    for (int e = tid; e < N * NH; e += NTP) {
+        const int row = e / NH, kx = e - row * NH;
+        gstore2(spec + row * sh + kx, buf[e]);
+    }
 }
 
 template <int N>
@@ -288,14 +293,16 @@ __global__ __launch_bounds__(NTP) void k_ifftxy(Batch B)
         twy[n] = gload2((gptr<const double2>)D.twy + n);
     }
     // inverse y transform by conjugation on the way in and out
-    const gptr<const double2> spec = (gptr<const double2>)D.spec + (long long)k * N * NH;
+    const int sh = D.sh;
+    const gptr<const double2> spec = (gptr<const double2>)D.spec + (long long)k * N * sh;
     {
         constexpr int MS = (N * NH + NTP - 1) / NTP;
         double2 v[MS];
 #pragma unroll
         for (int m = 0; m < MS; ++m) {
-            const int e = tid + m * NTP;
-            v[m] = gload2(spec + (e < N * NH ? e : 0));
+            const int e0 = tid + m * NTP, e = e0 < N * NH ? e0 : 0;
+            const int row = e / NH, kx = e - row * NH;
+            v[m] = gload2(spec + row * sh + kx);
         }
 #pragma unroll
         for (int m = 0; m < MS; ++m) {
@@ -356,13 +363,13 @@ __global__ __launch_bounds__(NT) void k_fft_strided(Batch B, int axis)
     const gptr<const double2> twg = (gptr<const double2>)(axis == 1 ? D.twy : D.twz);
     const gptr<double2> spec = (gptr<double2>)D.spec;
     for (int n = tid; n < N; n += NT) tw[n] = gload2(twg + n);
-    const int nh = D.nh, ny = D.ny;
+    const int nh = D.nh, sh = D.sh, ny = D.ny;
     const int ntk = (nh + TK - 1) / TK;
     const int tile = blockIdx.x % ntk, other = blockIdx.x / ntk;
     const int kx0 = tile * TK;
     long long base, es;
-    if (axis == 1) { base = (long long)other * ny * nh + kx0; es = nh; }
-    else { base = (long long)other * nh + kx0; es = (long long)nh * ny; }
+    if (axis == 1) { base = (long long)other * ny * sh + kx0; es = sh; }
+    else { base = (long long)other * sh + kx0; es = (long long)sh * ny; }
     const bool colok = kx0 + tid % TK < nh;
     tile_in<N, INV>(buf, spec + base, es, colok, tid);
     __syncthreads();
@@ -391,12 +398,12 @@ __global__ __launch_bounds__(NT) void k_solve_periodic(Batch B)
         ez[n] = eigz[n];
     }
     const gptr<double2> spec = (gptr<double2>)D.spec;
-    const int nh = D.nh, ny = D.ny;
+    const int nh = D.nh, sh = D.sh, ny = D.ny;
     const int ntk = (nh + TK - 1) / TK;
     const int tile = blockIdx.x % ntk, ky = blockIdx.x / ntk;
     const int kx0 = tile * TK;
     if (tid < TK) ex[tid] = kx0 + tid < nh ? eigx[kx0 + tid] : 0.0;
-    const long long base = (long long)ky * nh + kx0, es = (long long)nh * ny;
+    const long long base = (long long)ky * sh + kx0, es = (long long)sh * ny;
     const bool colok = kx0 + tid % TK < nh;
     tile_in<N, false>(buf, spec + base, es, colok, tid);
     __syncthreads();
@@ -429,13 +436,14 @@ template <int TH_P>
 __global__ __launch_bounds__(TH_NT) void k_thomas(Batch B)
 {
     const Desc& D = *B.d[blockIdx.y];
-    const int nh = D.nh, ny = D.ny, nz = D.nz;
+    const int nh = D.nh, sh = D.sh, ny = D.ny, nz = D.nz;
+    // lanes run over the padded rows, so each wave's modes start on a 128-byte line
     const int col = blockIdx.x * TH_NT + threadIdx.x;
-    if (col >= nh * nz) return;
-    const int kz = col / nh, kx = col - kz * nh;
+    const int kz = col / sh, kx = col - kz * sh;
+    if (kz >= nz || kx >= nh) return;
     const int kzs = kz <= nz - kz ? kz : nz - kz;
-    const gptr<const double> __restrict__ piv = (gptr<const double>)D.piv + (long long)kzs * ny * nh + kx;
-    const gptr<double2> __restrict__ s = (gptr<double2>)D.spec + (long long)kz * ny * nh + kx;
+    const gptr<const double> __restrict__ piv = (gptr<const double>)D.piv + (long long)kzs * ny * sh + kx;
+    const gptr<double2> __restrict__ s = (gptr<double2>)D.spec + (long long)kz * ny * sh + kx;
     const double a = D.idy * D.idy;                  // sub- and super-diagonal 1/dy^2
     const double scale = 1.0 / ((double)D.nx * nz);  // inverse x and z transforms
     // forward sweep d'_j = (r_j - a d'_{j-1}) / (b_j - a c'_{j-1}); the loads of the next block
@@ -447,8 +455,8 @@ __global__ __launch_bounds__(TH_NT) void k_thomas(Batch B)
 #pragma unroll
         for (int m = 0; m < TH_P; ++m) {
             const int jj = min(j0 + m, ny - 1);
-            rr[m] = gload2(s + (long long)jj * nh);
-            ii[m] = piv[(long long)jj * nh];
+            rr[m] = gload2(s + (long long)jj * sh);
+            ii[m] = piv[(long long)jj * sh];
         }
     };
     fload(0, r, iv);
@@ -458,7 +466,7 @@ __global__ __launch_bounds__(TH_NT) void k_thomas(Batch B)
         for (int m = 0; m < TH_P; ++m) {
             if (j0 + m < ny) {
                 dp = make_double2((scale * r[m].x - a * dp.x) * iv[m], (scale * r[m].y - a * dp.y) * iv[m]);
-                gstore2(s + (long long)(j0 + m) * nh, dp);
+                gstore2(s + (long long)(j0 + m) * sh, dp);
             }
         }
 #pragma unroll
@@ -472,8 +480,8 @@ __global__ __launch_bounds__(TH_NT) void k_thomas(Batch B)
 #pragma unroll
         for (int m = 0; m < TH_P; ++m) {
             const int jj = max(j1 - m, 0);
-            dd[m] = gload2(s + (long long)jj * nh);
-            cc[m] = a * piv[(long long)jj * nh];
+            dd[m] = gload2(s + (long long)jj * sh);
+            cc[m] = a * piv[(long long)jj * sh];
         }
     };
     if (ny >= 2) bload(ny - 2, r, iv);
@@ -483,7 +491,7 @@ __global__ __launch_bounds__(TH_NT) void k_thomas(Batch B)
         for (int m = 0; m < TH_P; ++m) {
             if (j1 - m >= 0) {
                 x = make_double2(r[m].x - iv[m] * x.x, r[m].y - iv[m] * x.y);
-                gstore2(s + (long long)(j1 - m) * nh, x);
+                gstore2(s + (long long)(j1 - m) * sh, x);
                 sum += x.x;
             }
         }
@@ -513,7 +521,7 @@ __global__ __launch_bounds__(NT) void k_ifftx(Batch B)
     const int nlines = D.ny * D.nz;
     const int npairs = (nlines + 1) >> 1;
     const int pair0 = blockIdx.x * LP;
-    const int nh = D.nh;
+    const int sh = D.sh;
     // Hermitian extension of two half spectra into one complex line; loads of eight elements are
     // issued before their LDS stores
     constexpr int M = (LP * N + NT - 1) / NT, G = M < 8 ? M : 8;
@@ -529,8 +537,8 @@ __global__ __launch_bounds__(NT) void k_ifftx(Batch B)
             const int la = pair < npairs ? 2 * pair : 0;
             const int lb = (pair < npairs && la + 1 < nlines) ? la + 1 : la;
             const int k = n <= N / 2 ? n : N - n;
-            av[m] = gload2(spec + (long long)la * nh + k);
-            bv[m] = gload2(spec + (long long)lb * nh + k);
+            av[m] = gload2(spec + (long long)la * sh + k);
+            bv[m] = gload2(spec + (long long)lb * sh + k);
         }
 #pragma unroll
         for (int m = 0; m < G; ++m) {
@@ -741,7 +749,7 @@ hipError_t launch_solve_periodic(const Batch& b, int nx, int ny, int nz, hipStre
 
 hipError_t launch_thomas(const Batch& b, int nx, int ny, int nz, hipStream_t s)
 {
-    const int cols = (nx / 2 + 1) * nz;
+    const int cols = (int)((nx / 2 + 1 + 7) / 8 * 8) * nz;   // padded rows (Desc::sh)
     dim3 grid((cols + TH_NT - 1) / TH_NT, b.count);
     // 16 rows ahead (248 VGPRs, two waves per SIMD): measured best against 8 and 32
     hipLaunchKernelGGL(k_thomas<16>, grid, dim3(TH_NT), 0, s, b);
