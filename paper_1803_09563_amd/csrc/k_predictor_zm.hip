@@ -476,13 +476,19 @@ __device__ __forceinline__ void pred_block(Smem<T>& S, const Batch& B, int freez
                 ox = ldx<BUF, T, kStream>(RU + kq, ob); oy = ldx<BUF, T, kStream>(RU + (kq + ps), ob);
                 oz = ldx<BUF, T, kStream>(RU + (kq + 2 * ps), ob);
             }
+            // the stress results are stored after the momentum part, so that the history loads
+            // above are in flight during it
+            auto store_stress = [&]() {
 #pragma unroll
-            for (int cc = 0; cc < 6; ++cc) {
-                stx<BUF, T>(Bout + (kq + cc * ps), ob, bt[cc] + dt * (c1 * rtv[cc] + c2 * old[cc]));
-                stx<BUF, T>(RT + (kq + cc * ps), ob, rtv[cc]);
+                for (int cc = 0; cc < 6; ++cc) {
+                    stx<BUF, T>(Bout + (kq + cc * ps), ob, bt[cc] + dt * (c1 * rtv[cc] + c2 * old[cc]));
+                    stx<BUF, T>(RT + (kq + cc * ps), ob, rtv[cc]);
+                }
+            };
+            if constexpr (!(sizeof(T) == 8 && !WALLS)) {
+                store_stress();
+                __asm__ volatile("" ::: "memory");
             }
-
-            __asm__ volatile("" ::: "memory");
             if constexpr (TWOPH) {
                 // the two-phase momentum follows in k_momentum_two_phase
             } else if (freeze) {
@@ -566,6 +572,7 @@ __device__ __forceinline__ void pred_block(Smem<T>& S, const Batch& B, int freez
                 }
                 stx<BUF, T>(RU + kq, ob, rux); stx<BUF, T>(RU + (kq + ps), ob, ruy); stx<BUF, T>(RU + (kq + 2 * ps), ob, ruz);
             }
+            if constexpr (sizeof(T) == 8 && !WALLS) store_stress();
 #undef VU
 #undef VV
 #undef VW
