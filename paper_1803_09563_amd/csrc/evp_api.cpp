@@ -48,7 +48,7 @@ bool is_23_smooth(int n)
 
 struct Layout {
     size_t desc, u, v, w, us, vs, ws, p, B0, B1, RT, RU, spec, twx, twy, twz, eigx, eigy, eigz,
-        piv, red, gauge, total;
+        piv, pvj, red, gauge, total;
     long long ps;
 };
 
@@ -80,6 +80,8 @@ bool shape_ok(int nx, int ny, int nz, int bc_y, int precision, std::string* why)
 // to 8, so that the 16-column tiles of the strided passes and the mode rows of the Thomas sweep
 // start on 128-byte lines
 size_t spectrum_stride(int nx) { return ((size_t)nx / 2 + 1 + 7) / 8 * 8; }
+// waves (blocks of 64 modes) of the Thomas kernel, which runs over the padded rows
+size_t thomas_waves(int nx, int nz) { return (spectrum_stride(nx) * (size_t)nz + 63) / 64; }
 
 Layout make_layout(int nx, int ny, int nz, int bc_y, int precision)
 {
@@ -103,6 +105,7 @@ Layout make_layout(int nx, int ny, int nz, int bc_y, int precision)
     L.twx = take((size_t)nx * 16); L.twy = take((size_t)ny * 16); L.twz = take((size_t)nz * 16);
     L.eigx = take(nh * 8); L.eigy = take((size_t)ny * 8); L.eigz = take((size_t)nz * 8);
     L.piv = take(bc_y == EVP_WALLS ? ((size_t)nz / 2 + 1) * ny * sh * 8 : 8);
+    L.pvj = take(bc_y == EVP_WALLS ? thomas_waves(nx, nz) * 4 : 4);
     L.red = take(kRedDoubles * 8);
     L.gauge = take(8);
     L.total = off;
@@ -262,6 +265,9 @@ void build_tables(const evp_grid* g, std::vector<char>& host, size_t base)
         const int ny = g->ny;
         const size_t sh = spectrum_stride(g->nx);
         const double a = 1.0 / (g->h.dy * g->h.dy);
+        // per mode, the first row from which every pivot up to row ny-2 equals the pivot of row
+        // ny-2 (the recurrence has reached its fixed point in floating point)
+        std::vector<int> conv((size_t)(g->nz / 2 + 1) * nh);
         for (int kzs = 0; kzs <= g->nz / 2; ++kzs) {
             for (int kx = 0; kx < nh; ++kx) {
                 const double mu = ex[kx] + ez[kzs];
@@ -274,7 +280,28 @@ void build_tables(const evp_grid* g, std::vector<char>& host, size_t base)
                     cprev = a * inv;
                 }
                 if (kx == 0 && kzs == 0) piv[(size_t)(ny - 1) * sh] = 0.0;   // singular mode: p_{ny-1} = 0
+                int J = ny >= 2 ? ny - 2 : 0;
+                if (ny >= 2) {
+                    const double last = piv[((size_t)kzs * ny + (ny - 2)) * sh + kx];
+                    while (J > 0 && piv[((size_t)kzs * ny + (J - 1)) * sh + kx] == last) --J;
+                }
+                conv[(size_t)kzs * nh + kx] = J;
             }
+        }
+        // per wave of the Thomas kernel (64 consecutive padded columns kz * sh + kx): the largest
+        // of its modes' rows, from which the kernel uses the converged pivot without loading it
+        int* pvj = reinterpret_cast<int*>(host.data() + (L.pvj - base));
+        const int nzz = g->nz, nw = (int)thomas_waves(g->nx, nzz);
+        for (int wv = 0; wv < nw; ++wv) {
+            int jw = 0;
+            for (int l = 0; l < 64; ++l) {
+                const long long col = (long long)wv * 64 + l;
+                const int kz = (int)(col / (long long)sh), kx = (int)(col % (long long)sh);
+                if (kz >= nzz || kx >= nh) continue;
+                const int kzs = kz <= nzz - kz ? kz : nzz - kz;
+                jw = std::max(jw, conv[(size_t)kzs * nh + kx]);
+            }
+            pvj[wv] = jw;
         }
     }
 }
@@ -586,6 +613,7 @@ int create_in(int nx, int ny, int nz, double lx, double ly, double lz, int bc_y,
     h.twx = (const double2*)(w + L.twx); h.twy = (const double2*)(w + L.twy); h.twz = (const double2*)(w + L.twz);
     h.eigx = (const double*)(w + L.eigx); h.eigy = (const double*)(w + L.eigy); h.eigz = (const double*)(w + L.eigz);
     h.piv = (const double*)(w + L.piv);
+    h.pvj = (const int*)(w + L.pvj);
     h.red = (double*)(w + L.red);
     h.gauge = (double*)(w + L.gauge);
     g->d = (Desc*)(w + L.desc);

@@ -44,6 +44,8 @@ struct Desc {
     const double2 *twx, *twy, *twz;        // W_N^n = exp(-2 pi i n / N), n < N, per direction
     const double *eigx, *eigy, *eigz;      // -(4/h^2) sin^2(pi k / N) per direction
     const double* piv;           // walls: Thomas pivots 1/(b_j - a c'_{j-1}) [nz/2+1][ny][sh]
+    const int* pvj;              // walls, per 64-mode wave of the Thomas solve: the row from which
+                                 // every pivot of its modes below row ny-1 equals row ny-2's
     double* red;                 // reduction partials (health)
     double* gauge;               // walls: volume mean of p before the zero-mean gauge (one value)
 };

@@ -446,6 +446,16 @@ __global__ __launch_bounds__(TH_NT) void k_thomas(Batch B)
     const gptr<double2> __restrict__ s = (gptr<double2>)D.spec + (long long)kz * ny * sh + kx;
     const double a = D.idy * D.idy;                  // sub- and super-diagonal 1/dy^2
     const double scale = 1.0 / ((double)D.nx * nz);  // inverse x and z transforms
+    // From row jc on (up to row ny-2) the pivot recurrence of every mode of this wave has reached
+    // its fixed point in floating point: those rows use the mode's pivot of row ny-2, loaded once,
+    // instead of a load per row (the same numbers)
+    const int jc = ((gptr<const int>)D.pvj)[blockIdx.x];
+    const double pinf = ny >= 2 ? piv[(long long)(ny - 2) * sh] : 0.0;
+    auto pivot = [&](int jj) {
+        double pv = pinf;
+        if (jj < jc || jj == ny - 1) pv = piv[(long long)jj * sh];
+        return pv;
+    };
     // forward sweep d'_j = (r_j - a d'_{j-1}) / (b_j - a c'_{j-1}); the loads of the next block
     // of TH_P rows are issued before the dependent updates of the current one
     double2 dp = make_double2(0.0, 0.0);
@@ -456,7 +466,7 @@ __global__ __launch_bounds__(TH_NT) void k_thomas(Batch B)
         for (int m = 0; m < TH_P; ++m) {
             const int jj = min(j0 + m, ny - 1);
             rr[m] = gload2(s + (long long)jj * sh);
-            ii[m] = piv[(long long)jj * sh];
+            ii[m] = pivot(jj);
         }
     };
     fload(0, r, iv);
@@ -481,7 +491,7 @@ __global__ __launch_bounds__(TH_NT) void k_thomas(Batch B)
         for (int m = 0; m < TH_P; ++m) {
             const int jj = max(j1 - m, 0);
             dd[m] = gload2(s + (long long)jj * sh);
-            cc[m] = a * piv[(long long)jj * sh];
+            cc[m] = a * pivot(jj);
         }
     };
     if (ny >= 2) bload(ny - 2, r, iv);
