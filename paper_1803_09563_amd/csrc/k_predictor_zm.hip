@@ -645,9 +645,11 @@ hipError_t launch_predictor_zm(const Batch& b, int precision, int nx, int ny, in
         if (in_hi > in_lo) parts[np++] = {true, {0, nty - (in_hi - in_lo), in_lo, in_hi - in_lo}};
         else parts[np++] = {true, {0, nty, 1 << 30, 0}};
     }
-    // The rows next to the walls run beside the interior on the side stream in the mixed form
-    // (measured faster for 256x128x128 and 512x256x256 channels); the FP64 wall kernel, which
-    // keeps more state per thread, competes worse for the CUs and runs after the interior.
+    // FP64 channels run both parts in one grid (k_pred_zm_channel).  In the mixed form the rows
+    // next to the walls run beside the interior on the side stream (measured faster for
+    // 256x128x128 and 512x256x256 channels: the FP32 wall and interior kernels differ in
+    // occupancy, so one grid would run both at the wall kernel's).  The two-phase mode launches
+    // the parts one after the other.
     if (np == 2 && precision == EVP_FP64 && !two_phase) {
         // one grid for both parts, chunked over all tile rows (see k_pred_zm_channel)
         const int kc = predictor_chunk_tiles(ntx * nty, nz, 2048);
