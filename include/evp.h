@@ -230,7 +230,11 @@ int evp_read_level_set(evp_grid* g, double* phi);
 /* Body force f of Eq. (NS), one of EVP_FORCE_*. */
 int evp_set_forcing(evp_grid* g, int kind, double amp, double ky);
 
-/* Wall velocities (EVP_WALLS only): x- and z-velocity of the bottom (y = -ly/2) and top walls. */
+/* Wall velocities (EVP_WALLS only): x- and z-velocity of the bottom (y = -ly/2) and top walls,
+ * the no-slip condition of the wall-bounded validation cases of Sec. 4 (walls at rest in the
+ * Poiseuille flow of Sec. 4.1.1, the default; walls moving in opposite directions in the plane
+ * Couette flow of the suspension case, Sec. 4.2).  The ghost velocities beyond a wall are
+ * reflected about these values.  EVP_ERR_ARG on a periodic grid or for non-finite values. */
 int evp_set_walls(evp_grid* g, double u_bot, double u_top, double w_bot, double w_top);
 
 /* Load the state: u, v, w (FP64 device arrays, layout above), B6 (six FP64 planes).  hist, if not
