@@ -101,6 +101,27 @@ def test_projection_parity(bc):
     assert div * min(s.g.dx, s.g.dy, s.g.dz) / umax < 1e-12
 
 
+@pytest.mark.parametrize("ny", [4, 17, 40, 256, 320])
+def test_projection_parity_wall_heights(ny):
+    """The channel solve over wall-normal sizes: one partly filled row segment (4), a last
+    segment of one row (17), a ragged one (40), all sixteen segments of a block (256), and the
+    sequential sweep that serves ny > 256 (320)."""
+    nx, nz = 16, 12
+    wl = _wl(nx, ny, nz, True, "oldroyd_b")
+    u, v, w, B = inputs.random_state(wl.shape, 23 + ny, walls=True)
+    s = oracle_solver(wl)
+    s.write_fields(u, v, w, B)
+    us, vs, ws, p = oracle.project(s.g, s.u, s.v, s.w, 1.0)
+    G = gpu_grid(wl)
+    G.write_fields(*to_dev(u, v, w, B))
+    G.project()
+    got = gpu_state(G, ("u", "v", "w", "p"))
+    assert_close({"u": us, "v": vs, "w": ws, "p": p}, got, 1e-12, f"projection walls ny={ny}")
+    div = np.abs(oracle.divergence(s.g, got["u"], got["v"], got["w"])).max()
+    umax = max(np.abs(got[k]).max() for k in "uvw")
+    assert div * min(s.g.dx, s.g.dy, s.g.dz) / umax < 1e-12
+
+
 def test_taylor_green_32_full_parity_100_steps():
     wl = inputs.taylor_green_periodic(32)
     u, v, w, B = inputs.initial_fields(wl)
