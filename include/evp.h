@@ -133,6 +133,8 @@ typedef struct {
     long long trace_ge95;  /* FENE-P cells with tr(B) >= 0.95 L^2 (Sec. 3.1); 0 for other models */
     double max_div;        /* max |D_h u| over cells */
     double energy;         /* 1/2 sum(u^2 + v^2 + w^2) dx dy dz over faces */
+    long long guard_bad;   /* workspace guard words no longer holding their pattern (a write past
+                              the end of a region); 0 on a sound grid */
 } evp_health_t;
 
 typedef struct {
@@ -150,6 +152,15 @@ const char* evp_last_error(void);
  * nx, nz: even, 8..512 and of the form 2^a 3^b (FFT directions); ny: 8..512 of the same form
  * when bc_y is EVP_PERIODIC, 4..1024 (any) with EVP_WALLS. */
 size_t evp_workspace_bytes(int nx, int ny, int nz, int bc_y, int precision);
+
+/* Guard regions of the workspace layout of a grid of this shape (a check for out-of-bounds writes,
+ * not part of the method): every region of the workspace is followed by 8-byte guard words that
+ * evp_create_grid fills with a fixed pattern and evp_health counts in guard_bad when they no longer
+ * hold it.  Writes up to max (byte offset from the workspace start, number of words) pairs into
+ * offsets[] and words[] (host memory, owned by the caller) and returns the number of regions, or
+ * EVP_ERR_ARG for an invalid shape.  Host only. */
+int evp_guard_regions(int nx, int ny, int nz, int bc_y, int precision, long long* offsets,
+                      long long* words, int max);
 
 /* Create a grid of nx x ny x nz cells in a box lx x ly x lz.  dev_workspace: device memory of at
  * least evp_workspace_bytes() bytes, 256-byte aligned, owned by the caller and kept alive until
@@ -283,11 +294,13 @@ int evp_save_state(evp_grid* g, void* dst, size_t bytes);
 int evp_load_state(evp_grid* g, const void* src, size_t bytes);
 
 /* Diagnostics of the current state; waits for the stream, *out is host memory.  The counts
- * follow the trigger conditions of the local artificial diffusion of Sec. 3.1. */
+ * follow the trigger conditions of the local artificial diffusion of Sec. 3.1; guard_bad counts
+ * overwritten workspace guard words (see evp_guard_regions). */
 int evp_health(evp_grid* g, evp_health_t* out);
 
-/* evp_health without waiting: enqueues the same diagnostics on the grid's stream and writes the
- * five values, as doubles in the order nonfinite, det_le0, trace_ge95, max_div, energy, into out5
+/* evp_health without waiting: enqueues the same diagnostics (all but guard_bad) on the grid's
+ * stream and writes the five values, as doubles in the order nonfinite, det_le0, trace_ge95,
+ * max_div, energy, into out5
  * (device memory of 5 doubles, owned by the caller).  out5 is valid once the stream has passed
  * this point (e.g. an event recorded after the call).  Same numbers as evp_health: the reduction
  * sums in a fixed order. */

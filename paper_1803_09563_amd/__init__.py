@@ -52,7 +52,8 @@ _d = ctypes.c_double
 
 class _Health(ctypes.Structure):
     _fields_ = [("nonfinite", ctypes.c_longlong), ("det_le0", ctypes.c_longlong),
-                ("trace_ge95", ctypes.c_longlong), ("max_div", _d), ("energy", _d)]
+                ("trace_ge95", ctypes.c_longlong), ("max_div", _d), ("energy", _d),
+                ("guard_bad", ctypes.c_longlong)]
 
 
 class TwoPhaseParams(ctypes.Structure):
@@ -71,6 +72,8 @@ symbols = {
     "evp_error_string": (ctypes.c_char_p, [_i]),
     "evp_last_error": (ctypes.c_char_p, []),
     "evp_workspace_bytes": (ctypes.c_size_t, [_i, _i, _i, _i, _i]),
+    "evp_guard_regions": (_i, [_i, _i, _i, _i, _i, ctypes.POINTER(ctypes.c_longlong),
+                               ctypes.POINTER(ctypes.c_longlong), _i]),
     "evp_create_grid": (_i, [_i, _i, _i, _d, _d, _d, _i, _i, _vp, ctypes.c_size_t, _vp,
                              ctypes.POINTER(_vp)]),
     "evp_create_grid_static": (_i, [_i, _i, _i, _d, _d, _d, _i, _i, _vp, ctypes.POINTER(_vp)]),
@@ -121,6 +124,17 @@ def _check(status: int, where: str):
 
 def workspace_bytes(nx, ny, nz, walls=False, precision=FP64) -> int:
     return int(lib.evp_workspace_bytes(nx, ny, nz, WALLS if walls else PERIODIC, precision))
+
+
+def guard_regions(nx, ny, nz, walls=False, precision=FP64):
+    """(byte offset, 8-byte words) of every guard region of this shape's workspace layout."""
+    bc = WALLS if walls else PERIODIC
+    n = lib.evp_guard_regions(nx, ny, nz, bc, precision, None, None, 0)
+    _check(min(n, 0), "evp_guard_regions")
+    off = (ctypes.c_longlong * n)()
+    words = (ctypes.c_longlong * n)()
+    _check(min(lib.evp_guard_regions(nx, ny, nz, bc, precision, off, words, n), 0), "evp_guard_regions")
+    return list(zip(off, words))
 
 
 def _torch():
@@ -311,7 +325,7 @@ class Grid:
         h = _Health()
         _check(lib.evp_health(self._h, ctypes.byref(h)), "evp_health")
         return {"nonfinite": h.nonfinite, "det_le0": h.det_le0, "trace_ge95": h.trace_ge95,
-                "max_div": h.max_div, "energy": h.energy}
+                "max_div": h.max_div, "energy": h.energy, "guard_bad": h.guard_bad}
 
     def health_enqueue(self, out5):
         """Enqueue the diagnostics on the grid's stream into out5, a float64 CUDA tensor of 5

@@ -46,10 +46,18 @@ bool is_23_smooth(int n)
     return n == 1;
 }
 
+// Every region is followed by guard words (the 8-byte words from the end of its data up to the
+// next 256-byte boundary, plus kGuardBytes), filled with evp::kGuardWord at creation and checked
+// by evp_health: a write past the end of a region lands on them.
+constexpr size_t kGuardBytes = 256;
+constexpr int kMaxGuards = 32;
+
 struct Layout {
     size_t desc, u, v, w, us, vs, ws, p, B0, B1, RT, RU, spec, twx, twy, twz, eigx, eigy, eigz,
-        piv, pvj, red, gauge, total;
+        piv, pvj, gtab, red, gauge, total;
     long long ps;
+    int ng;                        // guard regions: (byte offset, 8-byte words)
+    long long gd[kMaxGuards][2];
 };
 
 bool shape_ok(int nx, int ny, int nz, int bc_y, int precision, std::string* why)
@@ -92,7 +100,14 @@ Layout make_layout(int nx, int ny, int nz, int bc_y, int precision)
     const size_t tsz = precision == EVP_MIXED ? 4 : 8;
     L.ps = (long long)((n + 63) / 64 * 64);
     size_t off = 0;
-    auto take = [&](size_t bytes) { size_t o = off; off += align_up(bytes); return o; };
+    auto take = [&](size_t bytes) {
+        const size_t o = off, end = o + (bytes + 7) / 8 * 8;
+        off = o + align_up(bytes) + kGuardBytes;
+        L.gd[L.ng][0] = (long long)end;
+        L.gd[L.ng][1] = (long long)((off - end) / 8);
+        ++L.ng;
+        return o;
+    };
     L.desc = take(4096);
     L.u = take(n * 8); L.v = take(n * 8); L.w = take(n * 8);
     L.us = take(n * 8); L.vs = take(n * 8); L.ws = take(n * 8);
@@ -106,6 +121,7 @@ Layout make_layout(int nx, int ny, int nz, int bc_y, int precision)
     L.eigx = take(nh * 8); L.eigy = take((size_t)ny * 8); L.eigz = take((size_t)nz * 8);
     L.piv = take(bc_y == EVP_WALLS ? ((size_t)nz / 2 + 1) * ny * sh * 8 : 8);
     L.pvj = take(bc_y == EVP_WALLS ? thomas_waves(nx, nz) * 4 : 4);
+    L.gtab = take(kMaxGuards * 16);
     L.red = take(kRedDoubles * 8);
     L.gauge = take(8);
     L.total = off;
@@ -303,6 +319,12 @@ void build_tables(const evp_grid* g, std::vector<char>& host, size_t base)
             }
             pvj[wv] = jw;
         }
+    }
+    // guard table (byte offsets from the workspace start, word counts)
+    long long* gt = reinterpret_cast<long long*>(host.data() + (L.gtab - base));
+    for (int i = 0; i < L.ng; ++i) {
+        gt[2 * i] = L.gd[i][0];
+        gt[2 * i + 1] = L.gd[i][1];
     }
 }
 
@@ -553,6 +575,20 @@ size_t evp_workspace_bytes(int nx, int ny, int nz, int bc_y, int precision)
     return make_layout(nx, ny, nz, bc_y, precision).total;
 }
 
+int evp_guard_regions(int nx, int ny, int nz, int bc_y, int precision, long long* offsets,
+                      long long* words, int max)
+{
+    std::string why;
+    if (!shape_ok(nx, ny, nz, bc_y, precision, &why)) return fail(EVP_ERR_ARG, why);
+    const Layout L = make_layout(nx, ny, nz, bc_y, precision);
+    if (max > 0 && (!offsets || !words)) return fail(EVP_ERR_ARG, "offsets and words must be non-NULL");
+    for (int i = 0; i < L.ng && i < max; ++i) {
+        offsets[i] = L.gd[i][0];
+        words[i] = L.gd[i][1];
+    }
+    return L.ng;
+}
+
 }  // extern "C"
 
 namespace {
@@ -627,6 +663,9 @@ int create_in(int nx, int ny, int nz, double lx, double ly, double lz, int bc_y,
     build_tables(g, tables, L.twx);
     e = hipMemcpyAsync(w + L.twx, tables.data(), tables.size(), hipMemcpyHostToDevice, g->stream);
     if (e != hipSuccess) { delete g; return hip_fail(e, "table upload"); }
+    // guards last: the clear and the table image above cover some of them
+    e = evp::launch_guard_fill(w, (const long long*)(w + L.gtab), L.ng, g->stream);
+    if (e != hipSuccess) { delete g; return hip_fail(e, "workspace guards"); }
     int r = upload_desc(g);   // synchronises the stream (tables host buffer is released after)
     if (r) { delete g; return r; }
     *out = g;
@@ -956,7 +995,10 @@ int evp_health(evp_grid* g, evp_health_t* out)
     if (!out) return fail(EVP_ERR_ARG, "out is NULL");
     hipError_t e = evp::launch_health(g->d, g->precision, g->parity, nullptr, g->stream);
     if (e != hipSuccess) return hip_fail(e, "health");
-    double res[5];
+    e = evp::launch_guard_check(g->ws, (const long long*)(g->ws + g->L.gtab), g->L.ng, g->h.red + 1024 * 5 + 5,
+                                g->stream);
+    if (e != hipSuccess) return hip_fail(e, "guard check");
+    double res[6];
     e = hipMemcpyAsync(res, g->h.red + 1024 * 5, sizeof res, hipMemcpyDeviceToHost, g->stream);
     if (e != hipSuccess) return hip_fail(e, "health copy");
     e = hipStreamSynchronize(g->stream);
@@ -966,6 +1008,7 @@ int evp_health(evp_grid* g, evp_health_t* out)
     out->trace_ge95 = (long long)res[2];
     out->max_div = res[3];
     out->energy = res[4];
+    out->guard_bad = (long long)res[5];
     return EVP_OK;
 }
 

@@ -113,6 +113,14 @@ hipError_t launch_read_fields(const Desc* d, int precision, long long ncell, int
                               double* B6, double* hist, hipStream_t s);
 hipError_t launch_health(const Desc* d, int precision, int parity, double* out5, hipStream_t s);
 
+// Guard words after every region of a workspace: a fixed 64-bit pattern, a quiet NaN, so that a
+// stray read of one also shows up as a non-finite value.  table: n pairs (byte offset from ws,
+// number of 8-byte words), in device memory.  The check writes the number of words that no
+// longer hold the pattern to *out (as a double).
+constexpr unsigned long long kGuardWord = 0x7FF8DEADC0DE5AFEull;
+hipError_t launch_guard_fill(char* ws, const long long* table, int n, hipStream_t s);
+hipError_t launch_guard_check(const char* ws, const long long* table, int n, double* out, hipStream_t s);
+
 bool fft_size_supported(int n);
 
 }  // namespace evp

@@ -157,7 +157,51 @@ __global__ __launch_bounds__(HB) void k_health_final(const Desc* Dp, int nblocks
     }
 }
 
+// one block per guard region: every word gets the pattern
+__global__ __launch_bounds__(256) void k_guard_fill(gptr<unsigned long long> ws, gptr<const long long> table, int n)
+{
+    const int gi = blockIdx.x;
+    if (gi >= n) return;
+    const long long off = table[2 * gi] / 8, words = table[2 * gi + 1];
+    for (long long t = threadIdx.x; t < words; t += 256) ws[off + t] = kGuardWord;
+}
+
+// one block: count the words of every region that differ from the pattern, summed in a fixed
+// order
+__global__ __launch_bounds__(256) void k_guard_check(gptr<const unsigned long long> ws, gptr<const long long> table,
+                                                     int n, gptr<double> out)
+{
+    double bad = 0.0;
+    for (int gi = 0; gi < n; ++gi) {
+        const long long off = table[2 * gi] / 8, words = table[2 * gi + 1];
+        for (long long t = threadIdx.x; t < words; t += 256) bad += ws[off + t] != kGuardWord ? 1.0 : 0.0;
+    }
+    __shared__ double sh[256];
+    sh[threadIdx.x] = bad;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = sh[0];
+}
+
 }  // namespace
+
+hipError_t launch_guard_fill(char* ws, const long long* table, int n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_guard_fill, dim3(n), dim3(256), 0, s, (gptr<unsigned long long>)ws,
+                       (gptr<const long long>)table, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_guard_check(const char* ws, const long long* table, int n, double* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_guard_check, dim3(1), dim3(256), 0, s, (gptr<const unsigned long long>)ws,
+                       (gptr<const long long>)table, n, (gptr<double>)out);
+    return hipGetLastError();
+}
 
 hipError_t launch_write_fields(const Desc* d, int precision, long long ncell, int ny, int nx,
                                int walls, int parity, const double* u, const double* v,

@@ -33,9 +33,12 @@ def to_dev(*arrs):
 
 
 def gpu_state(G, which=("u", "v", "w", "p", "B")):
+    """Fields of a GPU grid as numpy arrays; also checks that no kernel has written past the end
+    of a workspace region (the guard words after every region are intact)."""
     import torch
     out = G.read_fields(which)
     torch.cuda.synchronize()
+    assert G.health()["guard_bad"] == 0, "a kernel wrote over workspace guard words"
     return {k: v.cpu().numpy() for k, v in out.items()}
 
 

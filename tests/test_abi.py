@@ -48,6 +48,22 @@ def test_workspace_covers_the_state():
     assert need <= got < need * 1.01
 
 
+def test_guard_regions_follow_every_region():
+    """Guard words after every workspace region (host-side layout query): each region ends on a
+    256-byte boundary followed by at least 256 bytes of guard words, regions and guards alternate,
+    and the last guard ends the workspace."""
+    for shape, walls, prec in [((64, 48, 32), True, evp.FP64), ((32, 32, 32), False, evp.MIXED)]:
+        regs = evp.guard_regions(*shape, walls=walls, precision=prec)
+        assert len(regs) >= 20
+        ends = [o + 8 * w for o, w in regs]
+        assert all(w >= 32 for _, w in regs)
+        assert all(e % 256 == 0 for e in ends)
+        assert all(regs[i + 1][0] > ends[i] for i in range(len(regs) - 1))
+        assert ends[-1] == evp.workspace_bytes(*shape, walls=walls, precision=prec)
+    with pytest.raises(evp.EvpError):
+        evp.guard_regions(30, 32, 32)
+
+
 def test_error_strings_and_argument_errors():
     assert evp.lib.evp_error_string(0) == b"ok"
     assert evp.lib.evp_error_string(-2).startswith(b"workspace")

@@ -102,7 +102,8 @@ def test_health_enqueue_equals_health():
     out = torch.empty(5, dtype=torch.float64, device="cuda")
     G.health_enqueue(out)
     torch.cuda.synchronize()
-    assert G.health_values(out) == G.health()
+    hv = G.health_values(out)
+    assert hv == {k: v for k, v in G.health().items() if k in hv}
 
 
 def test_budget_and_slots_bind():
