@@ -28,7 +28,9 @@ from dataclasses import dataclass
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# EVP_ORACLE_LIB selects another build of evp_oracle.c (the sanitizer test loads the ASan/UBSan
+# build made by build_sanitized in a child process)
+_LIB_PATH = os.environ.get("EVP_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 
 OLDROYD_B, FENE_P, SARAMITO, NEO_HOOKEAN = 0, 1, 2, 3
 WENO5, HOUC5 = 0, 1
@@ -47,6 +49,19 @@ def build(verbose: bool = False) -> str:
     subprocess.run(cmd, check=True)
     os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
+
+
+def build_sanitized(out: str) -> str:
+    """Compile ``evp_oracle.c`` with AddressSanitizer and UndefinedBehaviorSanitizer (every
+    finding fatal) into ``out``; a process loads it through EVP_ORACLE_LIB with gcc's libasan
+    preloaded."""
+    import subprocess
+    src = os.path.join(_HERE, "evp_oracle.c")
+    cmd = ["gcc", "-O1", "-g", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-fno-fast-math",
+           "-ffp-contract=off", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+           "-fno-sanitize-recover=all", src, "-o", out, "-lm"]
+    subprocess.run(cmd, check=True)
+    return out
 
 
 class _Params(ctypes.Structure):

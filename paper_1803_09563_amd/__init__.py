@@ -20,7 +20,8 @@ __all__ = ["Grid", "step_batch", "EvpError", "lib", "workspace_bytes", "symbols"
            "WENO5", "HOUC5", "STATIC_WORKSPACE_BYTES"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libevp.so")
+# EVP_LIB selects another build of the same library (the host-sanitizer test loads one)
+LIB_PATH = os.environ.get("EVP_LIB") or os.path.join(_HERE, "libevp.so")
 
 PERIODIC, WALLS = 0, 1
 FP64, MIXED = 0, 1
