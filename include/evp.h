@@ -149,8 +149,9 @@ const char* evp_error_string(int status);
 const char* evp_last_error(void);
 
 /* Bytes of device workspace a grid of this shape needs (0 if the arguments are invalid).
- * nx, nz: even, 8..512 and of the form 2^a 3^b (FFT directions); ny: 8..512 of the same form
- * when bc_y is EVP_PERIODIC, 4..1024 (any) with EVP_WALLS. */
+ * nx, nz (FFT directions): 2^a, 3 2^a, 5 2^a or 15 2^a in [8, 512] (8, 10, 12, 16, 20, 24, 30, 32,
+ * 40, 48, 60, 64, 80, 96, 120, 128, 160, 192, 240, 256, 320, 384, 480, 512); ny: one of the same
+ * sizes when bc_y is EVP_PERIODIC, 4..1024 (any) with EVP_WALLS. */
 size_t evp_workspace_bytes(int nx, int ny, int nz, int bc_y, int precision);
 
 /* Guard regions of the workspace layout of a grid of this shape (a check for out-of-bounds writes,

@@ -38,14 +38,6 @@ constexpr int kRedDoubles = 1024 * 5 + 8;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
-bool is_23_smooth(int n)
-{
-    if (n < 1) return false;
-    while (n % 2 == 0) n /= 2;
-    while (n % 3 == 0) n /= 3;
-    return n == 1;
-}
-
 // Every region is followed by guard words (the 8-byte words from the end of its data up to the
 // next 256-byte boundary, plus kGuardBytes), filled with evp::kGuardWord at creation and checked
 // by evp_health: a write past the end of a region lands on them.
@@ -66,15 +58,15 @@ bool shape_ok(int nx, int ny, int nz, int bc_y, int precision, std::string* why)
     if (bc_y != EVP_PERIODIC && bc_y != EVP_WALLS) { *why = "bc_y must be EVP_PERIODIC or EVP_WALLS"; return false; }
     if (precision != EVP_FP64 && precision != EVP_MIXED) { *why = "precision must be EVP_FP64 or EVP_MIXED"; return false; }
     if (nx % 2 != 0 || !evp::fft_size_supported(nx)) {
-        snprintf(buf, sizeof buf, "nx=%d: must be an even FFT size of the form 2^a 3^b in [8, 512]", nx);
+        snprintf(buf, sizeof buf, "nx=%d: must be an FFT size (2^a, 3 2^a, 5 2^a or 15 2^a in [8, 512])", nx);
         *why = buf; return false;
     }
     if (!evp::fft_size_supported(nz)) {
-        snprintf(buf, sizeof buf, "nz=%d: must be an FFT size of the form 2^a 3^b in [8, 512]", nz);
+        snprintf(buf, sizeof buf, "nz=%d: must be an FFT size (2^a, 3 2^a, 5 2^a or 15 2^a in [8, 512])", nz);
         *why = buf; return false;
     }
     if (bc_y == EVP_PERIODIC && !evp::fft_size_supported(ny)) {
-        snprintf(buf, sizeof buf, "ny=%d: periodic y needs an FFT size of the form 2^a 3^b in [8, 512]", ny);
+        snprintf(buf, sizeof buf, "ny=%d: periodic y needs an FFT size (2^a, 3 2^a, 5 2^a or 15 2^a in [8, 512])", ny);
         *why = buf; return false;
     }
     if (bc_y == EVP_WALLS && (ny < 4 || ny > 1024)) {

@@ -1,4 +1,4 @@
-// Mixed-radix (8, 4, 3, 2) FP64 complex FFT of one line held in LDS, computed cooperatively by a
+// Mixed-radix (8, 4, 3, 2, 5) FP64 complex FFT of one line held in LDS, computed cooperatively by a
 // group of threads: Stockham autosort stages, each thread reads its butterflies' inputs into
 // registers, the group synchronises, then writes the outputs back in place.  Forward transform
 // X_k = sum_n x_n exp(-2 pi i n k / N), unnormalised; the inverse is taken by conjugating data
@@ -41,13 +41,13 @@ struct FftPlan {
     int r[10];
 };
 
-// Greedy factorisation into radices 8, 4, 3, 2 (nst = -1 if another prime divides n).
+// Greedy factorisation into radices 8, 4, 3, 2, 5 (nst = -1 if another prime divides n).
 __host__ __device__ constexpr FftPlan make_plan(int n)
 {
     FftPlan p{n, 0, {0, 0, 0, 0, 0, 0, 0, 0, 0, 0}};
     int m = n;
     while (m > 1) {
-        int R = (m % 8 == 0) ? 8 : (m % 4 == 0) ? 4 : (m % 3 == 0) ? 3 : (m % 2 == 0) ? 2 : 0;
+        int R = (m % 8 == 0) ? 8 : (m % 4 == 0) ? 4 : (m % 3 == 0) ? 3 : (m % 2 == 0) ? 2 : (m % 5 == 0) ? 5 : 0;
         if (R == 0) { p.nst = -1; return p; }
         p.r[p.nst++] = R;
         m /= R;
@@ -80,6 +80,26 @@ template <> __device__ __forceinline__ void dft<4>(double2* v)
     double2 c = cadd(v[1], v[3]), d = cmi(csub(v[1], v[3]));
     v[0] = cadd(a, c); v[2] = csub(a, c);
     v[1] = cadd(b, d); v[3] = csub(b, d);
+}
+
+// X_k = sum_n x_n W_5^{nk}: with a_1 = x1 + x4, b_1 = x1 - x4, a_2 = x2 + x3, b_2 = x2 - x3,
+// X_{1,4} = x0 + c1 a1 + c2 a2 -/+ i (s1 b1 + s2 b2), X_{2,3} = x0 + c2 a1 + c1 a2 -/+ i (s2 b1 - s1 b2),
+// c_k = cos(2 pi k / 5), s_k = sin(2 pi k / 5)
+template <> __device__ __forceinline__ void dft<5>(double2* v)
+{
+    const double c1 = 0.30901699437494742410, c2 = -0.80901699437494742410;
+    const double s1 = 0.95105651629515357212, s2 = 0.58778525229247312917;
+    const double2 a1 = cadd(v[1], v[4]), b1 = csub(v[1], v[4]);
+    const double2 a2 = cadd(v[2], v[3]), b2 = csub(v[2], v[3]);
+    const double2 p1 = make_double2(v[0].x + c1 * a1.x + c2 * a2.x, v[0].y + c1 * a1.y + c2 * a2.y);
+    const double2 p2 = make_double2(v[0].x + c2 * a1.x + c1 * a2.x, v[0].y + c2 * a1.y + c1 * a2.y);
+    const double2 q1 = cmi(make_double2(s1 * b1.x + s2 * b2.x, s1 * b1.y + s2 * b2.y));   // -i (s1 b1 + s2 b2)
+    const double2 q2 = cmi(make_double2(s2 * b1.x - s1 * b2.x, s2 * b1.y - s1 * b2.y));   // -i (s2 b1 - s1 b2)
+    v[0] = cadd(v[0], cadd(a1, a2));
+    v[1] = cadd(p1, q1);
+    v[4] = csub(p1, q1);
+    v[2] = cadd(p2, q2);
+    v[3] = csub(p2, q2);
 }
 
 template <> __device__ __forceinline__ void dft<8>(double2* v)

@@ -798,6 +798,8 @@ bool fft_size_supported(int n)
     switch (n) {
     case 8: case 12: case 16: case 24: case 32: case 48: case 64: case 96: case 128: case 192:
     case 256: case 384: case 512:
+    case 10: case 20: case 30: case 40: case 60: case 80: case 120: case 160: case 240: case 320:
+    case 480:
         return true;
     default:
         return false;
@@ -819,6 +821,17 @@ bool fft_size_supported(int n)
     case 256: CALL(256); break;                                                                  \
     case 384: CALL(384); break;                                                                  \
     case 512: CALL(512); break;                                                                  \
+    case 10: CALL(10); break;                                                                    \
+    case 20: CALL(20); break;                                                                    \
+    case 30: CALL(30); break;                                                                    \
+    case 40: CALL(40); break;                                                                    \
+    case 60: CALL(60); break;                                                                    \
+    case 80: CALL(80); break;                                                                    \
+    case 120: CALL(120); break;                                                                  \
+    case 160: CALL(160); break;                                                                  \
+    case 240: CALL(240); break;                                                                  \
+    case 320: CALL(320); break;                                                                  \
+    case 480: CALL(480); break;                                                                  \
     default: return hipErrorInvalidValue;                                                        \
     }
 

@@ -31,10 +31,13 @@ def test_workspace_bytes_valid_and_invalid_shapes():
     b = evp.workspace_bytes(32, 32, 32, precision=evp.MIXED)
     c = evp.workspace_bytes(64, 48, 32, walls=True)
     assert a > 28 * 8 * 32 ** 3 and b < a and c > 0
-    assert evp.workspace_bytes(30, 32, 32) == 0          # 30 = 2*3*5: radix 5 unsupported
+    assert evp.workspace_bytes(30, 32, 32) > 0           # 30 = 2*3*5: radix-5 stage
+    assert evp.workspace_bytes(40, 20, 480) > 0          # 5 2^a and 15 2^a
+    assert evp.workspace_bytes(28, 32, 32) == 0          # 28 = 4*7: no radix 7
+    assert evp.workspace_bytes(36, 32, 32) == 0          # 36 = 4*9: not in the size list
     assert evp.workspace_bytes(31, 32, 32) == 0          # odd nx
-    assert evp.workspace_bytes(32, 20, 32) == 0          # periodic y needs an FFT size
-    assert evp.workspace_bytes(32, 20, 32, walls=True) > 0
+    assert evp.workspace_bytes(32, 28, 32) == 0          # periodic y needs an FFT size
+    assert evp.workspace_bytes(32, 28, 32, walls=True) > 0
     assert evp.workspace_bytes(32, 3, 32, walls=True) == 0
     assert evp.workspace_bytes(32, 32, 32, precision=7) == 0
 
@@ -61,7 +64,7 @@ def test_guard_regions_follow_every_region():
         assert all(regs[i + 1][0] > ends[i] for i in range(len(regs) - 1))
         assert ends[-1] == evp.workspace_bytes(*shape, walls=walls, precision=prec)
     with pytest.raises(evp.EvpError):
-        evp.guard_regions(30, 32, 32)
+        evp.guard_regions(28, 32, 32)
 
 
 def test_error_strings_and_argument_errors():
@@ -69,9 +72,9 @@ def test_error_strings_and_argument_errors():
     assert evp.lib.evp_error_string(-2).startswith(b"workspace")
     h = ctypes.c_void_p()
     # invalid shape is rejected before any device call
-    st = evp.lib.evp_create_grid(30, 32, 32, 1.0, 1.0, 1.0, 0, 0, ctypes.c_void_p(256), 1 << 30,
+    st = evp.lib.evp_create_grid(28, 32, 32, 1.0, 1.0, 1.0, 0, 0, ctypes.c_void_p(256), 1 << 30,
                                  None, ctypes.byref(h))
-    assert st == -1 and b"nx=30" in evp.lib.evp_last_error()
+    assert st == -1 and b"nx=28" in evp.lib.evp_last_error()
     st = evp.lib.evp_create_grid(32, 32, 32, 1.0, 1.0, 1.0, 0, 0, None, 1 << 30, None,
                                  ctypes.byref(h))
     assert st == -2

@@ -122,6 +122,47 @@ def test_projection_parity_wall_heights(ny):
     assert div * min(s.g.dx, s.g.dy, s.g.dz) / umax < 1e-12
 
 
+@pytest.mark.parametrize("shape", [(40, 20, 30, False), (10, 60, 20, False), (80, 12, 60, True),
+                                   (30, 9, 480, True), (320, 10, 8, False), (240, 6, 10, True)])
+def test_projection_parity_radix5(shape):
+    """Transform lengths with a radix-5 stage (5 2^a and 15 2^a) in x, y (periodic) and z."""
+    nx, ny, nz, walls = shape
+    wl = _wl(nx, ny, nz, walls, "oldroyd_b")
+    u, v, w, B = inputs.random_state(wl.shape, 31 + nx, walls=walls)
+    s = oracle_solver(wl)
+    s.write_fields(u, v, w, B)
+    us, vs, ws, p = oracle.project(s.g, s.u, s.v, s.w, 1.0)
+    G = gpu_grid(wl)
+    G.write_fields(*to_dev(u, v, w, B))
+    G.project()
+    got = gpu_state(G, ("u", "v", "w", "p"))
+    assert_close({"u": us, "v": vs, "w": ws, "p": p}, got, 1e-12, f"projection {shape}")
+    div = np.abs(oracle.divergence(s.g, got["u"], got["v"], got["w"])).max()
+    umax = max(np.abs(got[k]).max() for k in "uvw")
+    assert div * min(s.g.dx, s.g.dy, s.g.dz) / umax < 1e-12
+
+
+@pytest.mark.parametrize("walls", [False, True])
+def test_radix5_grid_steps_parity(walls):
+    """Saramito steps on a grid with radix-5 transform lengths: FP64 to 1e-10, mixed to 1e-4."""
+    nx, ny, nz = (40, 20, 30) if not walls else (60, 14, 40)
+    wl = _wl(nx, ny, nz, walls, "saramito")
+    u, v, w, B = inputs.random_state(wl.shape, 41, walls=walls)
+    s = oracle_solver(wl)
+    s.write_fields(u, v, w, B)
+    s.project()
+    s.step(1e-3, 10)
+    ref = oracle_state(s)
+    for prec, tol in (("fp64", 1e-10), ("mixed", 1e-4)):
+        import paper_1803_09563_amd as evp
+        G = gpu_grid(wl, precision=evp.FP64 if prec == "fp64" else evp.MIXED)
+        G.write_fields(*to_dev(u, v, w, B))
+        G.project()
+        G.step(1e-3, 10)
+        got = gpu_state(G)
+        assert_close(ref, got, tol, f"radix-5 grid {prec}", p_tol=1e-3 if prec == "mixed" else None)
+
+
 def test_taylor_green_32_full_parity_100_steps():
     wl = inputs.taylor_green_periodic(32)
     u, v, w, B = inputs.initial_fields(wl)
