@@ -90,8 +90,10 @@ def test_error_strings_and_argument_errors():
     assert evp.lib.evp_step(None, 1e-3, 1, 0) == -1
     assert evp.lib.evp_destroy_grid(None) == 0
     arr = (ctypes.c_void_p * 1)(None)
-    assert evp.lib.evp_step_batch(arr, 0, 1e-3, 1, 0) == -1
+    assert evp.lib.evp_step_batch(arr, 0, 1e-3, 1, 0) == -1          # empty batch
     assert evp.lib.evp_step_batch(arr, 1, 1e-3, 1, 0) == -1
+    big = (ctypes.c_void_p * (evp.MAX_BATCH + 1))()
+    assert evp.lib.evp_step_batch(big, evp.MAX_BATCH + 1, 1e-3, 1, 0) == -1   # above the maximum
 
 
 def test_no_cpu_fallback_in_package():

@@ -207,6 +207,25 @@ def test_radix5_grid_steps_parity(walls):
         assert_close(ref, got, tol, f"radix-5 grid {prec}", p_tol=1e-3 if prec == "mixed" else None)
 
 
+def test_zero_steps_change_nothing():
+    """Zero steps (alone and as a batch) leave the state and the step count exactly as they were."""
+    import paper_1803_09563_amd as evp
+    wl = _wl(32, 22, 24, True, "saramito")
+    u, v, w, B = inputs.random_state(wl.shape, 71, walls=True)
+    G = gpu_grid(wl)
+    G.write_fields(*to_dev(u, v, w, B))
+    G.project()
+    G.step(1e-3, 2)
+    which = ("u", "v", "w", "p", "B", "hist")
+    before, n0 = gpu_state(G, which), G.step_count()
+    G.step(1e-3, 0)
+    evp.step_batch([G], 1e-3, 0)
+    after = gpu_state(G, which)
+    assert G.step_count() == n0
+    for k in which:
+        assert np.array_equal(before[k], after[k]), k
+
+
 def test_taylor_green_32_full_parity_100_steps():
     wl = inputs.taylor_green_periodic(32)
     u, v, w, B = inputs.initial_fields(wl)
