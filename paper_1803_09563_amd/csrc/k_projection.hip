@@ -515,8 +515,8 @@ __global__ __launch_bounds__(TH_NT) void k_thomas(Batch B)
 
 // Segmented form of the same solve for ny <= TS_L * TS_SEG: a block holds TS_M modes, and each
 // group of TS_M lanes holds TS_L rows of them in registers (segment w of a block: rows
-// [TS_L w, TS_L w + TS_L)), so the spectrum is read once and written once.  Both sweeps are first-order linear
-// recurrences,
+// [TS_L w, TS_L w + TS_L)), so the spectrum is read once and written once.  Both sweeps are
+// first-order linear recurrences,
 //   forward   d'_j = s r_j iv_j + g_j d'_{j-1},
 //   backward  x_j  = d'_j + g_j x_{j+1}  (j <= ny-2; x_{ny-1} = d'_{ny-1}),  g_j = -a iv_j,
 // with |g_j| <= 1 (diagonally dominant rows).  Each segment runs its rows with a zero
