@@ -67,6 +67,37 @@ def test_guard_regions_follow_every_region():
         evp.guard_regions(28, 32, 32)
 
 
+FFT_SIZES = {8, 10, 12, 16, 20, 24, 30, 32, 40, 48, 60, 64, 80, 96, 120, 128, 160, 192, 240, 256,
+             320, 384, 480, 512}
+
+
+def test_shape_rules_hold_for_arbitrary_arguments():
+    """Property check of the host-side shape rules over arbitrary arguments: a workspace size (and
+    guard regions ending exactly at it) exactly when nx, nz and periodic ny are FFT sizes, walls
+    have 4 <= ny <= 1024, and the boundary type and precision are known; invalid arguments give 0
+    or an error status, never a crash."""
+    from hypothesis import given, settings, strategies as st
+
+    dims = st.one_of(st.sampled_from(sorted(FFT_SIZES)), st.integers(-8, 1100))
+
+    @settings(max_examples=400, deadline=None, derandomize=True)
+    @given(nx=dims, ny=dims, nz=dims, bc=st.integers(-1, 2), prec=st.integers(-1, 2))
+    def check(nx, ny, nz, bc, prec):
+        ok = (bc in (0, 1) and prec in (0, 1) and nx in FFT_SIZES and nz in FFT_SIZES
+              and (ny in FFT_SIZES if bc == 0 else 4 <= ny <= 1024))
+        got = evp.lib.evp_workspace_bytes(nx, ny, nz, bc, prec)
+        assert (got > 0) == ok, (nx, ny, nz, bc, prec, got)
+        n = evp.lib.evp_guard_regions(nx, ny, nz, bc, prec, None, None, 0)
+        assert (n > 0) == ok and (ok or n == -1)
+        if ok:
+            off = (ctypes.c_longlong * n)()
+            words = (ctypes.c_longlong * n)()
+            assert evp.lib.evp_guard_regions(nx, ny, nz, bc, prec, off, words, n) == n
+            assert off[n - 1] + 8 * words[n - 1] == got
+
+    check()
+
+
 def test_error_strings_and_argument_errors():
     assert evp.lib.evp_error_string(0) == b"ok"
     assert evp.lib.evp_error_string(-2).startswith(b"workspace")
