@@ -95,9 +95,11 @@ Layout make_layout(int nx, int ny, int nz, int bc_y, int precision)
     auto take = [&](size_t bytes) {
         const size_t o = off, end = o + (bytes + 7) / 8 * 8;
         off = o + align_up(bytes) + kGuardBytes;
-        L.gd[L.ng][0] = (long long)end;
-        L.gd[L.ng][1] = (long long)((off - end) / 8);
-        ++L.ng;
+        if (L.ng < kMaxGuards) {     // 24 regions today; the table holds kMaxGuards
+            L.gd[L.ng][0] = (long long)end;
+            L.gd[L.ng][1] = (long long)((off - end) / 8);
+            ++L.ng;
+        }
         return o;
     };
     L.desc = take(4096);
